@@ -1,0 +1,372 @@
+"""CPU reference (oracle) for the augmented-wavefield solve, the on-the-fly
+source-weight estimate, and the WRI objective and gradient.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or
+execute this module: it is used by the test-suite, by the smoke check and by the
+benchmark's CPU-baseline leg.  It shares no code with the GPU library (its only
+shared dependency is the seeded input generator ``wri_synth``, which holds no
+arithmetic of the method).
+
+Everything here is plain NumPy/SciPy in complex128 / float64, written from the
+paper's statement of the method (section "3D Source free wavefield
+reconstruction inversion"):
+
+* the Helmholtz operator A_j(m) = omega_j^2 diag(m) + Laplacian (text after
+  eq. FWI), with the 7-point second-order Laplacian, zero Dirichlet ghosts and
+  an m-independent damping sponge (read as -i*omega*diag(b));
+* the penalty objective (eq. ObjPen) in the scaling
+  J = sum ||A u - alpha e||^2 + lam^2 ||P u - d||^2, i.e. lam = 1/lambda_paper and
+  J = 2 f_2 / lambda_paper^2;
+* the closed-form minimiser over (u, alpha) for fixed m (eq. SimpObj, read with
+  conjugate transposes and P^H d), computed three independent ways;
+* the reduced objective (eq. VarObj2) and its gradient (eq. VarG2, read with
+  omega_j and a real part): g = sum 2 omega^2 Re(conj(u) * (A u - alpha e));
+* a reference CGLS (the CG-on-the-normal-equations reading of the paper's
+  Algorithm 1) with the stopping rule ||S^H r_k|| <= rtol ||S^H r_0||.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+KNOWN = "known"
+ESTIMATE = "estimate"
+
+
+# --------------------------------------------------------------------------
+# Operators (text after eq. FWI: A_j(m) = omega_j^2 diag(m) + Delta, P_i, e_i)
+# --------------------------------------------------------------------------
+
+def sponge(grid) -> np.ndarray:
+    """Damping profile b >= 0 (one value per cell, x fastest).
+
+    The paper is silent on the boundary; the workloads call for a "damped
+    boundary" of nb cells.  Reading: b = (2 d0 / v_ref^2) * sum over axes of
+    (delta/nb)^2, delta = distance (cells) into the sponge along that axis,
+    d0 = 3 v_ref ln(1000) / (2 nb h).  nb = 0 gives b = 0."""
+    if grid.nb <= 0:
+        return np.zeros(grid.n)
+    nb = float(grid.nb)
+    d0 = 3.0 * grid.v_ref * np.log(1000.0) / (2.0 * nb * grid.h)
+
+    def depth(n):
+        i = np.arange(n, dtype=np.float64)
+        return np.maximum(0.0, np.maximum(nb - i, i - (n - 1 - nb))) / nb
+
+    dz, dy, dx = np.meshgrid(depth(grid.nz), depth(grid.ny), depth(grid.nx), indexing="ij")
+    return ((2.0 * d0 / grid.v_ref ** 2) * (dx ** 2 + dy ** 2 + dz ** 2)).reshape(-1)
+
+
+def _second_difference(n: int, h: float) -> sp.csr_matrix:
+    """1D second difference (u[i-1] - 2u[i] + u[i+1]) / h^2, zero ghosts."""
+    e = np.ones(n)
+    return sp.diags([e[:-1], -2.0 * e, e[:-1]], [-1, 0, 1], shape=(n, n)) / h ** 2
+
+
+def laplacian(grid) -> sp.csr_matrix:
+    """7-point second-order Laplacian with zero Dirichlet ghosts, as the sum of
+    1D second differences along x, y and z (x fastest in the linear index)."""
+    Ix, Iy, Iz = (sp.identity(k, format="csr") for k in (grid.nx, grid.ny, grid.nz))
+    Dx, Dy, Dz = (_second_difference(k, grid.h) for k in (grid.nx, grid.ny, grid.nz))
+    L = sp.kron(Iz, sp.kron(Iy, Dx)) + sp.kron(Iz, sp.kron(Dy, Ix)) + sp.kron(Dz, sp.kron(Iy, Ix))
+    return L.tocsr()
+
+
+def helmholtz(grid, m: np.ndarray, omega: float, b: Optional[np.ndarray] = None) -> sp.csr_matrix:
+    """A = L_h + diag(omega^2 m - i omega b)   (complex128 CSR).
+
+    b defaults to the sponge profile of the grid; any non-negative array may
+    be passed (tests use a constant one)."""
+    if b is None:
+        b = sponge(grid)
+    diag = omega ** 2 * np.asarray(m, dtype=np.float64).reshape(-1) - 1j * omega * np.asarray(b).reshape(-1)
+    return (laplacian(grid).astype(np.complex128) + sp.diags(diag)).tocsr()
+
+
+def restriction(n: int, rec: np.ndarray) -> sp.csr_matrix:
+    """P: n_r x n selection of the receiver cells."""
+    rec = np.asarray(rec, dtype=np.int64)
+    return sp.csr_matrix((np.ones(rec.size), (np.arange(rec.size), rec)), shape=(rec.size, n),
+                         dtype=np.complex128)
+
+
+def unit_vector(n: int, src: int) -> np.ndarray:
+    e = np.zeros(n, dtype=np.complex128)
+    e[src] = 1.0
+    return e
+
+
+def system_operators(problem, k: int, m=None, b=None):
+    """(A, P, e) of system k, at model m (defaults to problem.m of its grid)."""
+    s = problem.systems[k]
+    g = problem.grids[s.grid]
+    mm = problem.m[s.grid] if m is None else m
+    A = helmholtz(g, mm, s.omega, b)
+    return A, restriction(g.n, s.rec), unit_vector(g.n, s.src)
+
+
+# --------------------------------------------------------------------------
+# Exact minimisers (eq. SimpObj and its KNOWN-source counterpart)
+# --------------------------------------------------------------------------
+
+def normal_matrix(A, P, lam) -> sp.csc_matrix:
+    """N = A^H A + lam^2 P^H P."""
+    AH = A.conj().T.tocsr()
+    return (AH @ A + lam ** 2 * (P.conj().T @ P)).tocsc()
+
+
+def factor(M):
+    return spl.splu(sp.csc_matrix(M), permc_spec="COLAMD")
+
+
+def solve_known(A, P, lam, alpha, e, d, lu=None) -> np.ndarray:
+    """u = argmin ||A u - alpha e||^2 + lam^2 ||P u - d||^2
+       = (A^H A + lam^2 P^H P)^{-1} (A^H (alpha e) + lam^2 P^H d)."""
+    lu = lu or factor(normal_matrix(A, P, lam))
+    rhs = A.conj().T @ (alpha * e) + lam ** 2 * (P.conj().T @ d)
+    return lu.solve(rhs)
+
+
+def solve_estimate(A, P, lam, src, d, route="varpro", lu=None) -> Tuple[np.ndarray, complex]:
+    """(u, alpha) = argmin over u and alpha of ||A u - alpha e||^2 + lam^2 ||P u - d||^2.
+
+    route "augmented": the (n+1) normal system of S = [[A, -e], [lam P, 0]],
+      b = [0; lam d]: [[N, -A^H e], [-e^H A, 1]] [u; alpha] = [lam^2 P^H d; 0].
+    route "varpro": u(alpha) = u0 + alpha u1 from the factor of N, then the
+      scalar least-squares problem in alpha.
+    route "projected": eliminate alpha first (its optimum is (A u)[src]), so
+      u minimises ||(I - e e^H) A u||^2 + lam^2 ||P u - d||^2.
+    """
+    n = A.shape[0]
+    e = unit_vector(n, src)
+    PH = P.conj().T
+    if route == "augmented":
+        N = normal_matrix(A, P, lam)
+        c = (A.conj().T @ e).reshape(-1, 1)
+        r = (e.conj() @ A).reshape(1, -1)
+        K = sp.bmat([[N, sp.csc_matrix(-c)], [sp.csc_matrix(-r), sp.csc_matrix([[1.0 + 0j]])]]).tocsc()
+        rhs = np.concatenate([lam ** 2 * (PH @ d), [0.0]])
+        x = factor(K).solve(rhs)
+        return x[:n], complex(x[n])
+    if route == "varpro":
+        lu = lu or factor(normal_matrix(A, P, lam))
+        u0 = lu.solve(lam ** 2 * (PH @ d))
+        u1 = lu.solve(A.conj().T @ e)
+        a = np.concatenate([A @ u1 - e, lam * (P @ u1)])
+        c = np.concatenate([-(A @ u0), lam * (d - P @ u0)])
+        alpha = complex(np.vdot(a, c) / np.vdot(a, a))
+        return u0 + alpha * u1, alpha
+    if route == "projected":
+        keep = np.ones(n)
+        keep[src] = 0.0
+        At = (sp.diags(keep) @ A).tocsr()
+        u = factor(normal_matrix(At, P, lam)).solve(lam ** 2 * (PH @ d))
+        return u, complex((A @ u)[src])
+    raise ValueError(route)
+
+
+def objective_terms(A, P, lam, u, alpha, e, d):
+    """(||A u - alpha e||^2, lam^2 ||P u - d||^2)."""
+    r1 = A @ u - alpha * e
+    r2 = P @ u - d
+    return float(np.vdot(r1, r1).real), float(lam ** 2 * np.vdot(r2, r2).real)
+
+
+def gradient_term(omega, u, A, alpha, e) -> np.ndarray:
+    """2 omega^2 Re(conj(u) * (A u - alpha e)) : one system's share of dJ/dm."""
+    return 2.0 * omega ** 2 * np.real(np.conj(u) * (A @ u - alpha * e))
+
+
+def objective_grad(problem, m_list=None, mode=None, route="varpro", b_list=None,
+                   return_fields=True) -> Dict:
+    """Exact variable-projection objective and gradient over all systems.
+
+    Returns dict(J, J_sys, g (list per grid, float64 (nz,ny,nx)), u (list),
+    alpha (array))."""
+    mode = mode or problem.mode
+    m_list = problem.m if m_list is None else m_list
+    grads = [np.zeros(g.n) for g in problem.grids]
+    us, alphas, Js = [None] * len(problem.systems), np.zeros(len(problem.systems), complex), \
+        np.zeros(len(problem.systems))
+    cache = {}
+    for k, s in enumerate(problem.systems):
+        g = problem.grids[s.grid]
+        b = None if b_list is None else b_list[s.grid]
+        key = (s.grid, s.freq, s.lam, tuple(np.asarray(s.rec).tolist()))
+        if key not in cache:
+            A = helmholtz(g, m_list[s.grid], s.omega, b)
+            P = restriction(g.n, s.rec)
+            cache = {key: (A, P, factor(normal_matrix(A, P, s.lam)))}
+        A, P, lu = cache[key]
+        e = unit_vector(g.n, s.src)
+        if mode == KNOWN:
+            u, alpha = solve_known(A, P, s.lam, s.alpha, e, s.d, lu=lu), s.alpha
+        else:
+            u, alpha = solve_estimate(A, P, s.lam, s.src, s.d, route=route,
+                                      lu=lu if route == "varpro" else None)
+        t1, t2 = objective_terms(A, P, s.lam, u, alpha, e, s.d)
+        Js[k] = t1 + t2
+        alphas[k] = alpha
+        grads[s.grid] += gradient_term(s.omega, u, A, alpha, e)
+        if return_fields:
+            us[k] = u
+    out = dict(J=float(Js.sum()), J_sys=Js, g=[gr.reshape(g.shape) for gr, g in zip(grads, problem.grids)],
+               alpha=alphas)
+    if return_fields:
+        out["u"] = us
+    return out
+
+
+def plain_helmholtz_solution(A, q) -> np.ndarray:
+    """u = A^{-1} q (the reduced-FWI wavefield, eq. PDEsolve)."""
+    return spl.splu(A.tocsc(), permc_spec="COLAMD").solve(q)
+
+
+def observed_data(problem, seed=0, noise=0.01) -> List[np.ndarray]:
+    """Clean data d = P A(m_true)^{-1} (alpha_true e) per system, plus noise
+    (via the generator's noise routine)."""
+    import wri_synth
+    rng = np.random.default_rng(seed + 1000)
+    out = []
+    cache = {}
+    for s in problem.systems:
+        g = problem.grids[s.grid]
+        key = (s.grid, s.freq)
+        if key not in cache:
+            A = helmholtz(g, problem.m_true[s.grid], s.omega)
+            cache = {key: spl.splu(A.tocsc(), permc_spec="COLAMD")}
+        lu = cache[key]
+        u = lu.solve(s.alpha * unit_vector(g.n, s.src))
+        d = u[np.asarray(s.rec)]
+        out.append(wri_synth.add_noise(d, rng, noise) if noise > 0 else d)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Residual of the normal equations and the reference CGLS (Algorithm 1 read as
+# CG on S^H S; convergence on ||S^H r_k|| / ||S^H r_0||)
+# --------------------------------------------------------------------------
+
+def apply_S(A, P, lam, src, mode, x):
+    """S x: KNOWN S = [A; lam P] (x = u); ESTIMATE S = [[A, -e], [lam P, 0]] (x = [u; alpha])."""
+    n = A.shape[0]
+    u = x[:n]
+    t1 = A @ u
+    if mode == ESTIMATE:
+        t1 = t1.copy()
+        t1[src] -= x[n]
+    return np.concatenate([t1, lam * (P @ u)])
+
+
+def apply_SH(A, P, lam, src, mode, r, AH=None, PH=None):
+    """S^H r for r = [r1 (n); r2 (n_r)]."""
+    n = A.shape[0]
+    AH = A.conj().T if AH is None else AH
+    PH = P.conj().T if PH is None else PH
+    s = AH @ r[:n] + lam * (PH @ r[n:])
+    if mode == ESTIMATE:
+        return np.concatenate([s, [-r[src]]])
+    return s
+
+
+def rhs_vector(n, lam, src, mode, alpha, d):
+    """b: KNOWN [alpha e; lam d]; ESTIMATE [0; lam d]."""
+    b1 = np.zeros(n, dtype=np.complex128)
+    if mode == KNOWN:
+        b1[src] = alpha
+    return np.concatenate([b1, lam * np.asarray(d, dtype=np.complex128)])
+
+
+def normal_residual(A, P, lam, src, mode, alpha_known, d, u, alpha=None) -> float:
+    """||S^H (b - S x)|| / ||S^H b|| in complex128 (x = u, or [u; alpha])."""
+    n = A.shape[0]
+    x = np.asarray(u, dtype=np.complex128)
+    if mode == ESTIMATE:
+        x = np.concatenate([x, [complex(alpha)]])
+    b = rhs_vector(n, lam, src, mode, alpha_known, d)
+    num = apply_SH(A, P, lam, src, mode, b - apply_S(A, P, lam, src, mode, x))
+    den = apply_SH(A, P, lam, src, mode, b)
+    dn = np.linalg.norm(den)
+    return float(np.linalg.norm(num) / dn) if dn > 0 else float(np.linalg.norm(num))
+
+
+def cgls(A, P, lam, src, mode, alpha_known, d, rtol, maxiter, vec_dtype=np.complex128,
+         time_limit=None):
+    """Reference CGLS on min ||S x - b||.
+
+    x0 = 0, r = b, s = S^H r, p = s, gamma = ||s||^2; per iteration
+    t = S p, a = gamma/||t||^2, x += a p, r -= a t, s = S^H r,
+    beta = ||s||^2/gamma, p = s + beta p.  Stops before forming t when
+    sqrt(gamma/gamma0) <= rtol.  Inner products and scalars are float64;
+    vectors are stored in vec_dtype (complex64 emulates the GPU's storage).
+
+    Returns dict(u, alpha, iters, relres, status, seconds)."""
+    t0 = time.perf_counter()
+    n = A.shape[0]
+    AH, PH = A.conj().T.tocsr(), P.conj().T.tocsr()
+    b = rhs_vector(n, lam, src, mode, alpha_known, d).astype(vec_dtype)
+    nx = n + (1 if mode == ESTIMATE else 0)
+
+    def dot(v):
+        v = v.astype(np.complex128, copy=False)
+        return float(np.vdot(v, v).real)
+
+    x = np.zeros(nx, dtype=vec_dtype)
+    r = b.copy()
+    s = apply_SH(A, P, lam, src, mode, r.astype(np.complex128), AH, PH).astype(vec_dtype)
+    p = s.copy()
+    gamma = dot(s)
+    gamma0 = gamma
+    k = 0
+    status = "converged"
+    if gamma0 == 0.0:
+        return dict(u=x[:n].astype(np.complex128), alpha=complex(x[n]) if mode == ESTIMATE else None,
+                    iters=0, relres=0.0, status="zero_rhs", seconds=time.perf_counter() - t0)
+    while True:
+        if np.sqrt(gamma / gamma0) <= rtol:
+            break
+        if k >= maxiter or (time_limit is not None and time.perf_counter() - t0 > time_limit):
+            status = "max_iter"
+            break
+        t = apply_S(A, P, lam, src, mode, p.astype(np.complex128)).astype(vec_dtype)
+        delta = dot(t)
+        if not np.isfinite(delta) or delta <= 0.0:
+            status = "breakdown"
+            break
+        a = gamma / delta
+        x = (x + a * p).astype(vec_dtype)
+        r = (r - a * t).astype(vec_dtype)
+        s = apply_SH(A, P, lam, src, mode, r.astype(np.complex128), AH, PH).astype(vec_dtype)
+        gnew = dot(s)
+        beta = gnew / gamma
+        gamma = gnew
+        p = (s + beta * p).astype(vec_dtype)
+        k += 1
+    x = x.astype(np.complex128)
+    return dict(u=x[:n], alpha=complex(x[n]) if mode == ESTIMATE else None, iters=k,
+                relres=float(np.sqrt(gamma / gamma0)), status=status,
+                r=r.astype(np.complex128), seconds=time.perf_counter() - t0)
+
+
+# --------------------------------------------------------------------------
+# The paper's own scaling (eqs. ObjPen, CmpctWRIobj, Sandb)
+# --------------------------------------------------------------------------
+
+def paper_S_and_b(A, P, src, d, lam_p):
+    """S = [[lam_p A, -lam_p e], [P, 0]], b = [0; d] exactly as printed."""
+    n = A.shape[0]
+    e = sp.csr_matrix(([1.0 + 0j], ([src], [0])), shape=(n, 1))
+    S = sp.bmat([[lam_p * A, -lam_p * e], [P, None]]).tocsr()
+    b = np.concatenate([np.zeros(n, np.complex128), np.asarray(d, np.complex128)])
+    return S, b
+
+
+def paper_f2(A, P, lam_p, u, alpha, e, d) -> float:
+    """f_2 = 1/2 (||P u - d||^2 + lam_p^2 ||A u - alpha e||^2)."""
+    r1 = A @ u - alpha * e
+    r2 = P @ u - d
+    return 0.5 * float(np.vdot(r2, r2).real + lam_p ** 2 * np.vdot(r1, r1).real)
