@@ -1,0 +1,191 @@
+"""Benchmark: source-frequency augmented solves per second on one MI355X.
+
+One step = one pass of the whole hot path over the batch: the batched
+source-estimating CGLS solve of all systems, the source-weight estimate, the
+objective and its gradient (wri_objective_grad).  Workload: the 128^3
+differentiation configuration (h = 10 m, sponge 10 cells, 16 sources on a 4x4
+surface grid x 5/7/9 Hz = 48 systems, 128 receivers in a vertical well,
+lambda = 0.12, rtol 1e-4), synthetic layered + anomaly model, inputs resident
+in HBM before the timed region.
+
+Also reported: the plain form (one system at a time, unfused kernels, host
+loop) on a sample of systems, per-kernel HBM roofline of the fused stencil
+launches (HIP events around every launch in one extra timed step), and the
+CPU oracle (complex128 CGLS) on a bounded sample.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-plain] [--no-cpu]
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "src·freq augmented solves/s at 128³, rtol 1e-4: batched vs plain; stencil GB/s"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per (system, cell) of one fused launch (complex64 = 8 B, m = 4 B):
+#   forward: read s, p_{k-1}, x, m; write p_k, t, x          -> 8*3 + 4 + 8*3 = 52
+#   adjoint: read r_k, t, m; write r_{k+1}, s                  -> 8*2 + 4 + 8*2 = 36
+BYTES_FWD = 52
+BYTES_ADJ = 36
+
+
+def _cpu_worker(args):
+    """Oracle CGLS (complex128, scipy CSR) on one system for a bounded time."""
+    name, k, tlimit, scale = args
+    import oracle
+    import wri_synth
+    p = wri_synth.make_config(name, seed=0)
+    s = p.systems[k]
+    A, P, e = oracle.system_operators(p, k)
+    t0 = time.perf_counter()
+    out = oracle.cgls(A, P, s.lam, s.src, "estimate", 0, s.d, rtol=s.rtol, maxiter=10 ** 9,
+                      time_limit=tlimit, alpha_scale=scale)
+    return out["iters"], out["seconds"], time.perf_counter() - t0
+
+
+def cpu_baseline(name, systems, mean_iters, seconds, h):
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    procs = max(1, min(16, ncpu, len(systems)))
+    scale = 42.0 ** 0.5 / h ** 2
+    with mp.get_context("spawn").Pool(procs) as pool:
+        outs = pool.map(_cpu_worker, [(name, k, seconds, scale) for k in systems[:procs]])
+    it_per_s = sum(it / max(sec, 1e-9) for it, sec, _ in outs)
+    solves_per_s = it_per_s / mean_iters
+    return {"value": solves_per_s, "unit": "solves/s", "cores": procs, "kind": "oracle",
+            "sample": (f"oracle complex128 CGLS (scipy CSR mat-vecs) on {procs} of the {name} systems, one "
+                       f"process per core, {seconds:.0f} s each ({sum(o[0] for o in outs)} iterations total, "
+                       f"{it_per_s:.2f} it/s aggregate); solves/s = it/s / {mean_iters:.0f} (mean GPU "
+                       f"iterations per solve at rtol 1e-4)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="differentiation")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--plain-sample", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(systems are independent; see DESIGN.md for how the batch would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import wri_synth
+    from paper_2410_18429_amd import wri
+
+    dev = "cuda:0"
+    prob = wri_synth.make_config(args.config, seed=0)
+    g = prob.grids[0]
+    nsys = len(prob.systems)
+    batch = wri.Batch(prob, device=dev)
+    n_cells = sum(batch.grid_cells(s.grid) for s in prob.systems)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    log(f"[bench] {args.config}: {nsys} systems, grid {g.nx}x{g.ny}x{g.nz}")
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        J, grads, res = wri.objective_grad(batch)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f} s, iters mean "
+            f"{np.mean([r['iters'] for r in res]):.0f}")
+
+    torch.cuda.synchronize()
+    times = []
+    t_all = time.perf_counter()
+    for k in range(args.steps):
+        t0 = time.perf_counter()
+        J, grads, res = wri.objective_grad(batch)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"[bench] step {k}: {times[-1]:.3f} s  J={J:.6e}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    ms_step = 1000.0 * total / args.steps
+    value = nsys / (total / args.steps)
+    iters = np.array([r["iters"] for r in res])
+    statuses = sorted(set(r["status"] for r in res))
+
+    # per-kernel timing: one more step with an event pair around every fused launch
+    wri.objective_grad(batch, flags=wri.FLAG_TIMING)
+    torch.cuda.synchronize()
+    kt = wri.kernel_times()
+    fwd_gbs = BYTES_FWD * kt["cell_iters"] / (kt["fwd_ms"] * 1e-3) / 1e9
+    adj_gbs = BYTES_ADJ * kt["cell_iters"] / (kt["adj_ms"] * 1e-3) / 1e9
+    log(f"[bench] kernels: fwd {kt['fwd_ms'] / kt['fwd_launches']:.3f} ms/launch ({fwd_gbs:.0f} GB/s), "
+        f"adj {kt['adj_ms'] / kt['adj_launches']:.3f} ms/launch ({adj_gbs:.0f} GB/s)")
+    dominant = "fwd" if kt["fwd_ms"] >= kt["adj_ms"] else "adj"
+    ach = fwd_gbs if dominant == "fwd" else adj_gbs
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_fwd (fused forward CGLS stencil)" if dominant == "fwd" else
+                          "k_adj (fused adjoint CGLS stencil)",
+                "avg_launch_ms": round((kt["fwd_ms"] / kt["fwd_launches"]) if dominant == "fwd"
+                                       else (kt["adj_ms"] / kt["adj_launches"]), 4),
+                "fwd_gbs": round(fwd_gbs, 1), "adj_gbs": round(adj_gbs, 1),
+                "bytes_per_cell_iter": {"fwd": BYTES_FWD, "adj": BYTES_ADJ}}
+
+    plain = None
+    if not args.no_plain and args.plain_sample > 0:
+        freqs = sorted(set(s.freq for s in prob.systems))
+        pick = [next(i for i, s in enumerate(prob.systems) if s.freq == f) for f in freqs][:args.plain_sample]
+        pb = wri.Batch(prob.subset(pick), device=dev)
+        wri.objective_grad(pb, flags=wri.FLAG_PLAIN)     # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, pres = wri.objective_grad(pb, flags=wri.FLAG_PLAIN)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        bt = wri.Batch(prob.subset(pick), device=dev)
+        wri.objective_grad(bt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, bres = wri.objective_grad(bt)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t1
+        plain = {"value": len(pick) / tp, "unit": "solves/s", "systems": pick,
+                 "iters": [r["iters"] for r in pres],
+                 "same_systems_batched": len(pick) / tb,
+                 "sample": f"systems {pick} (one per frequency), one at a time, unfused kernels, host loop"}
+        log(f"[bench] plain: {plain['value']:.3f} solves/s on {pick}; batched same systems "
+            f"{plain['same_systems_batched']:.3f}")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] cpu baseline ...")
+        cpu = cpu_baseline(args.config, list(range(0, nsys, max(1, nsys // 16))), float(iters.mean()),
+                           args.cpu_seconds, g.h)
+        log(f"[bench] cpu: {cpu['value']:.5f} solves/s on {cpu['cores']} cores")
+
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {g.nx}x{g.ny}x{g.nz} h={g.h:g} m, "
+                               f"{nsys} systems (16 sources x 5/7/9 Hz), ESTIMATE, rtol 1e-4, "
+                               f"solve + source estimate + J + gradient per step",
+                   "systems": nsys, "cells_per_system": g.n, "reductions": "f64",
+                   "iters_mean": float(iters.mean()), "iters_min": int(iters.min()), "iters_max": int(iters.max()),
+                   "status": statuses, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "batched_vs_plain": round(value / plain["value"], 3) if plain else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

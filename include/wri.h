@@ -1,0 +1,216 @@
+/*
+ * wri.h — C ABI of the MI355X (gfx950) augmented-wavefield library.
+ *
+ * The library solves, for many (source i, frequency j) systems at once, the
+ * data-augmented wavefield problem of wavefield reconstruction inversion
+ * (paper: "3D Source free wavefield reconstruction inversion", eqs. ObjPen,
+ * CmpctWRIobj/Sandb, SimpObj):
+ *
+ *     J_ij(u, a) = || A_j(m) u - a e_i ||^2 + lambda^2 || P_i u - d_ij ||^2
+ *
+ * A_j(m) = L_h + diag(omega_j^2 m - i omega_j b)  (text after eq. FWI):
+ *   L_h  the 7-point second-order Laplacian with zero Dirichlet ghosts,
+ *   m    squared slowness [s^2/m^2] (float32, one value per cell),
+ *   b    an m-independent damping sponge of nb cells on every face:
+ *        b = (2 d0 / v_ref^2) * sum_axes (delta_axis / nb)^2, delta_axis the
+ *        distance (cells) into the sponge, d0 = 3 v_ref ln(1000) / (2 nb h).
+ * P_i samples the receiver cells, e_i is the unit vector of the source cell.
+ *
+ * lambda here weights the DATA term (lambda = 1/lambda_paper; the paper's
+ * f_2 equals lambda_paper^2 J / 2).
+ *
+ * Two modes:
+ *   WRI_KNOWN    a = alpha given:   minimise over u; normal equations
+ *                (A^H A + lambda^2 P^H P) u = A^H (alpha e) + lambda^2 P^H d.
+ *   WRI_ESTIMATE a unknown (the paper's source-free / on-the-fly source
+ *                estimate, eq. SimpObj): minimise over x = [u; a].
+ * Both are solved by CGLS on S = [[A, -c e],[lambda P, 0]] with x = [u; a/c]
+ * (KNOWN: S = [A; lambda P]) — the conjugate-gradient-on-the-normal-equations
+ * reading of the paper's Algorithm 1 — from x0 = 0, stopping when
+ * ||S^H r_k|| <= rtol ||S^H r_0||.  c = sqrt(42)/h^2 (the norm of a Laplacian
+ * column) equilibrates the source column; c = 1 is the printed S (same
+ * minimiser).
+ * Vectors are stored as complex float32; the stencil and vector-update
+ * arithmetic runs in float64 registers (one rounding per stored value); every
+ * inner product, step scalar, the unknown source weight and the objective are
+ * float64.
+ *
+ * Objective and gradient (eqs. VarObj2, VarG2): J = sum_ij J_ij at the
+ * computed minimiser (from the CGLS recurred residuals r1 = q - A u and
+ * r2 = lambda (d - P u)), and, because b does not depend on m,
+ *     dJ/dm = sum_ij 2 omega_j^2 Re( conj(u_ij) * (A_j u_ij - a_ij e_i) ).
+ *
+ * Conventions shared by every entry point
+ *   - Cell layout: x fastest, linear index (z*ny + y)*nx + x, z down.
+ *   - Complex numbers are interleaved (re, im).
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory owned by the caller.  The library
+ *     never frees caller memory.  Scratch comes from the caller's workspace
+ *     (size from wri_workspace_bytes); the only library-global state is the
+ *     tile autotune cache and cached HIP graphs (guarded by a mutex).
+ *   - `stream` is a hipStream_t; all device work is ordered on it.  The
+ *     solver entry points synchronise `stream` before returning (their
+ *     per-system results are written to host memory).
+ *   - Return value: 0 = OK; 1 = WRI_NOT_CONVERGED (some system stopped at
+ *     max_iter, see results); < 0 = error.  Inputs are validated before any
+ *     device work; on error nothing is launched and wri_last_error() gives a
+ *     message (thread-local).  No C++ exception crosses this ABI.
+ */
+#ifndef WRI_H
+#define WRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } wri_c32;
+typedef struct { double re, im; } wri_c64;
+
+/* One grid. nx*ny*nz < 2^31 cells; h > 0 [m]; nb >= 0 sponge cells;
+ * v_ref > 0 [m/s] (sponge reference velocity; ignored when nb == 0). */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t nb;
+  double  h;
+  double  v_ref;
+} wri_grid;
+
+/* One (source, frequency) system = one right-hand side. */
+typedef struct {
+  int32_t        grid;    /* index into the grids array                         */
+  int32_t        src;     /* linear cell index of the point source e_i          */
+  double         omega;   /* angular frequency 2*pi*f [rad/s], >= 0             */
+  double         lambda;  /* data weight (>= 0)                                 */
+  double         rtol;    /* tolerance on ||S^H r_k|| / ||S^H r_0||, >= 0       */
+  wri_c64        alpha;   /* source weight, used in WRI_KNOWN only              */
+  int32_t        n_rec;   /* number of receivers (>= 0)                         */
+  int32_t        _pad;
+  const int32_t* rec;     /* HOST, n_rec distinct linear cell indices (P_i)     */
+  const wri_c32* d;       /* DEVICE, n_rec observed data d_ij                   */
+} wri_system;
+
+/* Per-system results (host). */
+typedef struct {
+  int32_t iters;          /* CGLS iterations performed (S p products)           */
+  int32_t status;         /* WRI_SYS_*                                          */
+  double  relres;         /* recurred sqrt(gamma_k / gamma_0)                   */
+  double  J;              /* ||r1||^2 + ||r2||^2 from the recurred residuals    */
+  wri_c64 alpha;          /* source weight of the solution: KNOWN: the input;
+                             ESTIMATE: the CGLS unknown                         */
+  wri_c64 alpha_ls;       /* ESTIMATE: least-squares weight for the computed u,
+                             (A u)[src] (the exact stationarity condition in a);
+                             KNOWN: the input                                   */
+} wri_result;
+
+enum { WRI_KNOWN = 0, WRI_ESTIMATE = 1 };
+
+enum {
+  WRI_OK = 0,
+  WRI_NOT_CONVERGED = 1,
+  WRI_EINVAL = -1,      /* bad argument (null pointer, size, mode, ...)       */
+  WRI_ERANGE = -2,      /* a cell index (src or receiver) outside its grid    */
+  WRI_EDUP = -3,        /* duplicate receiver indices within one system       */
+  WRI_ENOWS = -4,       /* workspace missing or smaller than required         */
+  WRI_EHIP = -5,        /* a HIP runtime call failed                          */
+  WRI_EBREAKDOWN = -6   /* some system broke down (non-finite or <= 0 curvature) */
+};
+
+enum {
+  WRI_SYS_CONVERGED = 0,
+  WRI_SYS_MAX_ITER = 1,
+  WRI_SYS_BREAKDOWN = 2,
+  WRI_SYS_ZERO_RHS = 3   /* S^H b = 0: the solution is x = 0, no iteration   */
+};
+
+/* flags (bitwise OR) */
+enum {
+  WRI_FLAG_PLAIN = 1,       /* one system at a time, unfused kernels, host-driven
+                               scalars (the straightforward transcription of the
+                               iterative solver; the baseline of the batched form) */
+  WRI_FLAG_NO_GRAPH = 2,    /* launch the batched iterations eagerly (no hipGraph) */
+  WRI_FLAG_NO_AUTOTUNE = 4, /* use the default slab tile instead of the tuned one */
+  WRI_FLAG_UNSCALED_ALPHA = 8, /* ESTIMATE: use the source column -e exactly as printed
+                               (default: -c e with c = sqrt(42)/h^2, same minimiser,
+                               better-conditioned iteration) */
+  WRI_FLAG_TIMING = 16      /* launch the batched iterations eagerly with a HIP event
+                               pair around every fused launch; totals via
+                               wri_kernel_times() */
+};
+
+/* Workspace bytes needed by wri_solve / wri_objective_grad / estimate_source
+ * for these systems (host-only computation; no device call).  Returns 0 and
+ * sets wri_last_error() if the arguments are invalid. */
+size_t wri_workspace_bytes(const wri_grid* grids, int32_t n_grids,
+                           const wri_system* sys, int32_t n_sys,
+                           int32_t mode, int32_t flags);
+
+/* Validate arguments only (host-only; no device call).  Same checks and
+ * return codes as the solver entry points. */
+int wri_validate(const wri_grid* grids, int32_t n_grids,
+                 const wri_system* sys, int32_t n_sys,
+                 int32_t mode, int32_t max_iter);
+
+/* Batched augmented solve (eq. SimpObj; paper's grouping of systems, eq.
+ * Mmatrix2 read as block-diagonal).  All systems — any mix of sources,
+ * frequencies and grids — iterate together; each stops at its own rtol.
+ *   m[g]      DEVICE float32, n(g) squared slowness of grid g (n_grids pointers, host array)
+ *   u_out     host array of n_sys DEVICE pointers (n(grid) complex each) receiving u,
+ *             or NULL (u is then kept in the workspace only)
+ *   res       HOST, n_sys results (required)
+ *   ws        DEVICE workspace of ws_bytes >= wri_workspace_bytes(...) */
+int wri_solve(const wri_grid* grids, int32_t n_grids, const float* const* m,
+              const wri_system* sys, int32_t n_sys, int32_t mode, int32_t max_iter,
+              int32_t flags, wri_c32* const* u_out, wri_result* res,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* Objective and gradient in m (eqs. VarObj2, VarG2): runs the batched solve,
+ * then writes
+ *   J_out     HOST double, sum over systems of J_ij
+ *   grad[g]   DEVICE float32 n(g): dJ/dm on grid g, summed over the systems on
+ *             that grid (overwritten; grids without systems get zeros)
+ *   u_out, res as in wri_solve (u_out may be NULL). */
+int wri_objective_grad(const wri_grid* grids, int32_t n_grids, const float* const* m,
+                       const wri_system* sys, int32_t n_sys, int32_t mode, int32_t max_iter,
+                       int32_t flags, double* J_out, float* const* grad,
+                       wri_c32* const* u_out, wri_result* res,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* On-the-fly source-weight estimate (section "3D Source free wavefield
+ * reconstruction inversion", variable projection of eq. SimpObj): an
+ * ESTIMATE-mode solve, then alpha_out[k] = (A u_k)[src_k] in float64 — the
+ * weight that minimises J_k for the computed wavefield.
+ *   alpha_out HOST, n_sys; u_out optional as in wri_solve. */
+int estimate_source(const wri_grid* grids, int32_t n_grids, const float* const* m,
+                    const wri_system* sys, int32_t n_sys, int32_t max_iter, int32_t flags,
+                    wri_c64* alpha_out, wri_c32* const* u_out, wri_result* res,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Single operator application (text after eq. FWI): out = A in (adjoint = 0)
+ * or out = A^H in (adjoint = 1) on one grid.  in, out: DEVICE, n complex,
+ * distinct buffers; m: DEVICE float32 n.  Uses the solver's stencil code. */
+int wri_apply_helmholtz(const wri_grid* grid, const float* m, double omega,
+                        const wri_c32* in, wri_c32* out, int32_t adjoint, void* stream);
+
+/* Kernel time of the last WRI_FLAG_TIMING call on this thread: summed
+ * durations [ms] and launch counts of the fused forward and adjoint launches
+ * (one launch covers every active system of one grid), and the number of
+ * (system, cell) updates each kind performed in full.  Returns WRI_EINVAL if
+ * no timed call has run on this thread. */
+int wri_kernel_times(double* fwd_ms, int64_t* fwd_launches, double* adj_ms, int64_t* adj_launches,
+                     int64_t* cell_iters);
+
+/* Text of a return code; message of the last error on this thread. */
+const char* wri_strerror(int code);
+const char* wri_last_error(void);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int wri_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WRI_H */

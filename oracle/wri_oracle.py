@@ -251,25 +251,27 @@ def observed_data(problem, seed=0, noise=0.01) -> List[np.ndarray]:
 # CG on S^H S; convergence on ||S^H r_k|| / ||S^H r_0||)
 # --------------------------------------------------------------------------
 
-def apply_S(A, P, lam, src, mode, x):
-    """S x: KNOWN S = [A; lam P] (x = u); ESTIMATE S = [[A, -e], [lam P, 0]] (x = [u; alpha])."""
+def apply_S(A, P, lam, src, mode, x, c=1.0):
+    """S x: KNOWN S = [A; lam P] (x = u); ESTIMATE S = [[A, -c e], [lam P, 0]]
+    (x = [u; alpha / c]; c = 1 is the paper's S, any c > 0 has the same
+    minimiser in (u, alpha))."""
     n = A.shape[0]
     u = x[:n]
     t1 = A @ u
     if mode == ESTIMATE:
         t1 = t1.copy()
-        t1[src] -= x[n]
+        t1[src] -= c * x[n]
     return np.concatenate([t1, lam * (P @ u)])
 
 
-def apply_SH(A, P, lam, src, mode, r, AH=None, PH=None):
+def apply_SH(A, P, lam, src, mode, r, AH=None, PH=None, c=1.0):
     """S^H r for r = [r1 (n); r2 (n_r)]."""
     n = A.shape[0]
     AH = A.conj().T if AH is None else AH
     PH = P.conj().T if PH is None else PH
     s = AH @ r[:n] + lam * (PH @ r[n:])
     if mode == ESTIMATE:
-        return np.concatenate([s, [-r[src]]])
+        return np.concatenate([s, [-c * r[src]]])
     return s
 
 
@@ -295,7 +297,7 @@ def normal_residual(A, P, lam, src, mode, alpha_known, d, u, alpha=None) -> floa
 
 
 def cgls(A, P, lam, src, mode, alpha_known, d, rtol, maxiter, vec_dtype=np.complex128,
-         time_limit=None):
+         time_limit=None, alpha_scale=1.0):
     """Reference CGLS on min ||S x - b||.
 
     x0 = 0, r = b, s = S^H r, p = s, gamma = ||s||^2; per iteration
@@ -317,14 +319,15 @@ def cgls(A, P, lam, src, mode, alpha_known, d, rtol, maxiter, vec_dtype=np.compl
 
     x = np.zeros(nx, dtype=vec_dtype)
     r = b.copy()
-    s = apply_SH(A, P, lam, src, mode, r.astype(np.complex128), AH, PH).astype(vec_dtype)
+    c = float(alpha_scale)
+    s = apply_SH(A, P, lam, src, mode, r.astype(np.complex128), AH, PH, c).astype(vec_dtype)
     p = s.copy()
     gamma = dot(s)
     gamma0 = gamma
     k = 0
     status = "converged"
     if gamma0 == 0.0:
-        return dict(u=x[:n].astype(np.complex128), alpha=complex(x[n]) if mode == ESTIMATE else None,
+        return dict(u=x[:n].astype(np.complex128), alpha=c * complex(x[n]) if mode == ESTIMATE else None,
                     iters=0, relres=0.0, status="zero_rhs", seconds=time.perf_counter() - t0)
     while True:
         if np.sqrt(gamma / gamma0) <= rtol:
@@ -332,7 +335,7 @@ def cgls(A, P, lam, src, mode, alpha_known, d, rtol, maxiter, vec_dtype=np.compl
         if k >= maxiter or (time_limit is not None and time.perf_counter() - t0 > time_limit):
             status = "max_iter"
             break
-        t = apply_S(A, P, lam, src, mode, p.astype(np.complex128)).astype(vec_dtype)
+        t = apply_S(A, P, lam, src, mode, p.astype(np.complex128), c).astype(vec_dtype)
         delta = dot(t)
         if not np.isfinite(delta) or delta <= 0.0:
             status = "breakdown"
@@ -340,14 +343,14 @@ def cgls(A, P, lam, src, mode, alpha_known, d, rtol, maxiter, vec_dtype=np.compl
         a = gamma / delta
         x = (x + a * p).astype(vec_dtype)
         r = (r - a * t).astype(vec_dtype)
-        s = apply_SH(A, P, lam, src, mode, r.astype(np.complex128), AH, PH).astype(vec_dtype)
+        s = apply_SH(A, P, lam, src, mode, r.astype(np.complex128), AH, PH, c).astype(vec_dtype)
         gnew = dot(s)
         beta = gnew / gamma
         gamma = gnew
         p = (s + beta * p).astype(vec_dtype)
         k += 1
     x = x.astype(np.complex128)
-    return dict(u=x[:n], alpha=complex(x[n]) if mode == ESTIMATE else None, iters=k,
+    return dict(u=x[:n], alpha=c * complex(x[n]) if mode == ESTIMATE else None, iters=k,
                 relres=float(np.sqrt(gamma / gamma0)), status=status,
                 r=r.astype(np.complex128), seconds=time.perf_counter() - t0)
 

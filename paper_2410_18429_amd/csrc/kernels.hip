@@ -1,0 +1,943 @@
+// HIP kernels (gfx950) of the augmented-wavefield solver.
+//
+// The hot loop is CGLS on S = [[A, -e],[lambda P, 0]] (KNOWN: [A; lambda P]),
+// the conjugate-gradient-on-the-normal-equations reading of the paper's
+// Algorithm 1, whose cost is dominated by the products S p and S^H r
+// ("GPU acceleration" section).  Each iteration is two fused, bandwidth-bound
+// launches over every active system:
+//
+//   fwd (k):  x += a_{k-1} p_{k-1};  p_k = s_k + beta_k p_{k-1};
+//             t = S p_k (7-point stencil + source column + receiver gather);
+//             float64 partials of ||t||^2.
+//   adj (k):  a_k = gamma_k / ||t||^2;  r_{k+1} = r_k - a_k t;
+//             s_{k+1} = S^H r_{k+1} (stencil + receiver scatter, s_alpha = -r1[src]);
+//             float64 partials of ||s_{k+1}||^2.
+//
+// A workgroup owns a 64 x TY x TZ slab tile of one system: lanes run along x
+// (coalesced 512-byte rows of complex64), waves stack along y, and the tile
+// marches along z with the (z-1, z, z+1) column values in registers and the
+// current x-y plane (plus a one-cell halo) in LDS.  The neighbour values of the
+// updated vector (p_k in fwd, r_{k+1} in adj) are recomputed from the stored
+// inputs at halo cells, so the updated vector never needs a grid-wide barrier
+// before the stencil.
+//
+// Scalars: every workgroup of a system sums the previous launch's per-tile
+// partials in the same fixed order, so all workgroups derive bit-identical
+// float64 scalars (no atomics, deterministic for a given tiling).
+#include "wri_impl.hpp"
+
+#include <cfloat>
+#include <climits>
+
+namespace wri {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // Blocks go round-robin to the XCDs; give each XCD a contiguous range of
+  // logical tiles so that halo re-reads of neighbouring tiles hit its L2.
+  const int xcd = b % kXCD, local = b / kXCD;
+  const int per = nb / kXCD, rem = nb % kXCD;
+  return xcd * per + min(xcd, rem) + local;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of n partials by one wave in a fixed order, broadcast to the block.
+template <int NW>
+__device__ __forceinline__ double block_sum_slots(const double* __restrict__ p, int n, double* red) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    double v = 0.0;
+    for (int i = tid; i < n; i += 64) v += p[i];
+    v = wave_sum(v);
+    if (tid == 0) red[NW] = v;
+  }
+  __syncthreads();
+  const double r = red[NW];
+  __syncthreads();
+  return r;
+}
+
+// Block reduction; the result is valid in thread 0 only.
+template <int NW>
+__device__ __forceinline__ double block_reduce(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r += red[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+// Squared sponge depth along one axis, in units of nb (0 outside the sponge).
+__device__ __forceinline__ float sponge_axis(int i, int n, int nb, float inv_nb) {
+  const int d = max(0, max(nb - i, i - (n - 1 - nb)));
+  const float f = (float)d * inv_nb;
+  return f * f;
+}
+__device__ __forceinline__ double sponge_axis_d(int i, int n, int nb, double inv_nb) {
+  const int d = max(0, max(nb - i, i - (n - 1 - nb)));
+  const double f = (double)d * inv_nb;
+  return f * f;
+}
+
+// One cell of A c (kim = -omega b) or A^H c (kim = +omega b):
+//   sum over the 6 neighbours of (nb - c) / h^2  +  (omega^2 m + i kim) c.
+// Storage is complex float32; the arithmetic is float64 in registers and the
+// result is rounded once.  (Float32 arithmetic here loses several digits to
+// cancellation between the Laplacian and the mass term and slows CGLS; the
+// kernels are bandwidth-bound, so the float64 pipe costs nothing measurable.)
+// The difference form limits cancellation for smooth fields.  This function
+// is the only place the stencil arithmetic lives, so every tiling (and the
+// single-operator kernel) rounds identically.
+__device__ __forceinline__ double2 helm(float2 c, float2 xm, float2 xp, float2 ym, float2 yp,
+                                        float2 zm, float2 zp, double h2inv, double kre, double kim) {
+  const double cr = c.x, ci = c.y;
+  const double lr = ((((double)xm.x - cr) + ((double)xp.x - cr)) + (((double)ym.x - cr) + ((double)yp.x - cr))) +
+                    (((double)zm.x - cr) + ((double)zp.x - cr));
+  const double li = ((((double)xm.y - ci) + ((double)xp.y - ci)) + (((double)ym.y - ci) + ((double)yp.y - ci))) +
+                    (((double)zm.y - ci) + ((double)zp.y - ci));
+  return make_double2(lr * h2inv + (kre * cr - kim * ci), li * h2inv + (kre * ci + kim * cr));
+}
+
+__device__ __forceinline__ float2 round2(double2 v) { return make_float2((float)v.x, (float)v.y); }
+
+__device__ __forceinline__ float2 f2(float a, float b) { return make_float2(a, b); }
+// y + a x in float64 arithmetic, rounded once to complex float32
+__device__ __forceinline__ float2 axpy2(float2 y, double a, float2 x) {
+  return f2((float)((double)y.x + a * (double)x.x), (float)((double)y.y + a * (double)x.y));
+}
+__device__ __forceinline__ double norm2d(float2 v) {
+  return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+}
+
+// ---------------------------------------------------------------------------
+// initialisation: x = 0, p0 = 0, r1 = b1 (KNOWN: alpha e; ESTIMATE: 0),
+// r2 = lambda d, state reset.  grid = (blocks per system, nsys).
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, SysState* __restrict__ stv) {
+  const int rhs = blockIdx.y;
+  const SysDev& S = sysv[rhs];
+  const int n = S.nx * S.ny * S.nz;
+  const float2 z = f2(0.f, 0.f);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    S.x[c] = z;
+    S.p[0][c] = z;
+    float2 r = z;
+    if (S.mode == 0 && c == S.src) r = f2((float)S.alpha.x, (float)S.alpha.y);
+    S.r[1][c] = r;
+  }
+  if (blockIdx.x == 0) {
+    for (int q = threadIdx.x; q < S.n_rec; q += blockDim.x) {
+      const float2 dq = S.d[q];
+      S.r2[q] = f2((float)(S.lam_d * dq.x), (float)(S.lam_d * dq.y));
+      S.t2[q] = z;
+    }
+    if (threadIdx.x == 0) {
+      SysState* T = stv + rhs;
+      T->gamma[0] = T->gamma[1] = 0.0;
+      T->gamma0 = 0.0;
+      T->a[0] = T->a[1] = 0.0;
+      T->xa = make_double2(0.0, 0.0);
+      T->pa = make_double2(0.0, 0.0);
+      T->sa = make_double2(0.0, 0.0);
+      T->J = 0.0;
+      T->alpha_ls = make_double2(0.0, 0.0);
+      T->iterA = 0;
+      T->iterB = -1;
+      T->status = kActive;
+      T->iters = 0;
+    }
+  }
+}
+
+hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s) {
+  if (nsys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init, dim3(256, nsys), dim3(256), 0, s, sys, st);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry shared by the fused kernels
+// ---------------------------------------------------------------------------
+
+template <int W, int RY>
+struct TileCtx {
+  static constexpr int TY = W * RY;
+  static constexpr int LX = kTX + 2;
+  static constexpr int LY = TY + 2;
+  static constexpr int NH = 2 * LX + 2 * TY;  // halo cells of one plane
+  int x0, y0, z0, z1;
+  int gx;
+  int gy[RY];
+  bool in[RY];
+  int plane;  // nx*ny
+
+  __device__ void setup(const SysDev& S, int tile, int lane, int w, int tiles_x, int tiles_y, int tz) {
+    const int txi = tile % tiles_x;
+    const int rem = tile / tiles_x;
+    const int tyi = rem % tiles_y;
+    const int tzi = rem / tiles_y;
+    x0 = txi * kTX;
+    y0 = tyi * TY;
+    z0 = tzi * tz;
+    z1 = min(z0 + tz, S.nz);
+    gx = x0 + lane;
+    plane = S.nx * S.ny;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      gy[j] = y0 + w * RY + j;
+      in[j] = (gx < S.nx) && (gy[j] < S.ny);
+    }
+  }
+  // LDS halo slot h -> (hx, hy) in LDS coordinates
+  __device__ static void halo_xy(int h, int& hx, int& hy) {
+    if (h < LX) { hx = h; hy = 0; }
+    else if (h < 2 * LX) { hx = h - LX; hy = LY - 1; }
+    else { const int h2 = h - 2 * LX; hy = 1 + (h2 >> 1); hx = (h2 & 1) ? (LX - 1) : 0; }
+  }
+};
+
+// Per-thread receiver cursors for its RY columns.
+template <int RY>
+struct RecCursor {
+  int cur[RY], end[RY], nz_[RY];
+  __device__ void setup(const SysDev& S, int gx, const int* gy, const bool* in, int z0) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      cur[j] = 0; end[j] = 0; nz_[j] = INT_MAX;
+      if (S.colmap != nullptr && in[j]) {
+        const int2 be = S.colmap[gy[j] * S.nx + gx];
+        int c = be.x;
+        while (c < be.y && S.entries[c].x < z0) ++c;
+        cur[j] = c; end[j] = be.y;
+        nz_[j] = (c < be.y) ? S.entries[c].x : INT_MAX;
+      }
+    }
+  }
+  __device__ int take(const SysDev& S, int j) {  // receiver index at the current z; advance
+    const int q = S.entries[cur[j]].y;
+    ++cur[j];
+    nz_[j] = (cur[j] < end[j]) ? S.entries[cur[j]].x : INT_MAX;
+    return q;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// fused forward kernel: x update, p update, t = S p, ||t||^2 partials
+// ---------------------------------------------------------------------------
+
+template <int W, int RY>
+__global__ void __launch_bounds__(64 * W)
+k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_s,
+      double* __restrict__ part_d, int rhs0, int ntiles, int tiles_x, int tiles_y, int tz) {
+  using Ctx = TileCtx<W, RY>;
+  __shared__ float2 pl[2][Ctx::LY][Ctx::LX];
+  __shared__ double red[W + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int rl = logical / ntiles;
+  const int tile = logical - rl * ntiles;
+  const int rhs = rhs0 + rl;
+  const SysDev& S = sysv[rhs];
+  SysState* T = stv + rhs;
+  if (T->status != kActive) return;
+  const int k = T->iterA;
+
+  const double gk = block_sum_slots<W>(part_s + S.slot_base, ntiles, red);
+  const double g0 = (k == 0) ? gk : T->gamma0;
+  const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter);
+  const double beta = (k == 0) ? 0.0 : gk / T->gamma[(k - 1) & 1];
+  const double aprev = (k == 0) ? 0.0 : T->a[(k - 1) & 1];
+  if (tile == 0 && tid == 0) {
+    T->gamma[k & 1] = gk;
+    if (k == 0) T->gamma0 = gk;
+    T->iterB = k;
+  }
+
+  Ctx C;
+  C.setup(S, tile, lane, w, tiles_x, tiles_y, tz);
+  const int plane = C.plane;
+  const double af = aprev;
+  const double bf = beta;
+  const double w2 = S.omega_d * S.omega_d;
+  const float2* __restrict__ sv = S.s;
+  const float2* __restrict__ po = S.p[k & 1];
+  float2* __restrict__ pn = S.p[(k + 1) & 1];
+  float2* __restrict__ xv = S.x;
+
+  // source cell: which of my rows (if any) holds it
+  const int sxy = S.src % plane, sz = S.src / plane;
+  const int sx = sxy % S.nx, sy = sxy / S.nx;
+  int srcj = -1;
+  if (S.mode == 1 && sx == C.gx && sz >= C.z0 && sz < C.z1) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+      if (C.gy[j] == sy) srcj = j;
+  }
+
+  if (stop) {
+    // finish x with the last step; the adjoint kernel records the status
+    if (aprev != 0.0) {
+      for (int z = C.z0; z < C.z1; ++z) {
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+          if (!C.in[j]) continue;
+          const int c = z * plane + C.gy[j] * S.nx + C.gx;
+          xv[c] = axpy2(xv[c], af, po[c]);
+        }
+      }
+      if (srcj >= 0) {
+        const double2 pa = T->pa;
+        T->xa = make_double2(T->xa.x + aprev * pa.x, T->xa.y + aprev * pa.y);
+      }
+    }
+    return;
+  }
+
+  // source-weight direction p_a = s_a + beta p_a (owned by the source thread)
+  double2 pa_new = make_double2(0.0, 0.0);
+  if (srcj >= 0) {
+    const double2 pa = T->pa, sa = T->sa;
+    pa_new = make_double2(sa.x + beta * pa.x, sa.y + beta * pa.y);
+    T->xa = make_double2(T->xa.x + aprev * pa.x, T->xa.y + aprev * pa.y);
+  }
+
+  RecCursor<RY> rc;
+  rc.setup(S, C.gx, C.gy, C.in, C.z0);
+
+  double sxy2[RY];
+  const double sx2 = sponge_axis_d(C.gx, S.nx, S.nb, S.inv_nb_d);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
+
+  auto pval = [&](int c) -> float2 { return axpy2(sv[c], bf, po[c]); };
+
+  float2 pm[RY], pc[RY], pnx[RY], poc[RY], pon[RY];
+  // plane z0 - 1 and z0
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    pm[j] = f2(0.f, 0.f);
+    pc[j] = f2(0.f, 0.f);
+    poc[j] = f2(0.f, 0.f);
+    if (C.in[j]) {
+      const int c = C.z0 * plane + C.gy[j] * S.nx + C.gx;
+      if (C.z0 > 0) pm[j] = pval(c - plane);
+      poc[j] = po[c];
+      pc[j] = axpy2(sv[c], bf, poc[j]);
+    }
+    pl[0][1 + w * RY + j][1 + lane] = pc[j];
+  }
+  for (int h = tid; h < Ctx::NH; h += 64 * W) {
+    int hx, hy;
+    Ctx::halo_xy(h, hx, hy);
+    const int xx = C.x0 + hx - 1, yy = C.y0 + hy - 1;
+    float2 v = f2(0.f, 0.f);
+    if (xx >= 0 && xx < S.nx && yy >= 0 && yy < S.ny) v = pval(C.z0 * plane + yy * S.nx + xx);
+    pl[0][hy][hx] = v;
+  }
+  __syncthreads();
+
+  double acc = 0.0;
+  int cur = 0;
+  for (int z = C.z0; z < C.z1; ++z) {
+    const int nxt = cur ^ 1;
+    const bool has_next = (z + 1) < S.nz;
+    // plane z+1: own cells and halo
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      pnx[j] = f2(0.f, 0.f);
+      pon[j] = f2(0.f, 0.f);
+      if (C.in[j] && has_next) {
+        const int c = (z + 1) * plane + C.gy[j] * S.nx + C.gx;
+        pon[j] = po[c];
+        pnx[j] = axpy2(sv[c], bf, pon[j]);
+      }
+    }
+    for (int h = tid; h < Ctx::NH; h += 64 * W) {
+      int hx, hy;
+      Ctx::halo_xy(h, hx, hy);
+      const int xx = C.x0 + hx - 1, yy = C.y0 + hy - 1;
+      float2 v = f2(0.f, 0.f);
+      if (has_next && xx >= 0 && xx < S.nx && yy >= 0 && yy < S.ny)
+        v = pval((z + 1) * plane + yy * S.nx + xx);
+      pl[nxt][hy][hx] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < RY; ++j) pl[nxt][1 + w * RY + j][1 + lane] = pnx[j];
+
+    // t = S p at plane z
+    const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      if (!C.in[j]) continue;
+      const int ly = w * RY + j;
+      const int c = z * plane + C.gy[j] * S.nx + C.gx;
+      const float2 xm = pl[cur][ly + 1][lane];
+      const float2 xp = pl[cur][ly + 1][lane + 2];
+      const float2 ym = (j > 0) ? pc[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
+      const float2 yp = (j < RY - 1) ? pc[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
+      const double b = S.sp_scale_d * (sxy2[j] + sz2);
+      double2 td = helm(pc[j], xm, xp, ym, yp, pm[j], pnx[j], S.h2inv_d, w2 * (double)S.m[c], -(S.omega_d * b));
+      if (j == srcj && z == sz) {
+        td.x -= S.alpha_c * pa_new.x;
+        td.y -= S.alpha_c * pa_new.y;
+      }
+      const float2 tv = round2(td);
+      S.t[c] = tv;
+      pn[c] = pc[j];
+      if (aprev != 0.0) xv[c] = axpy2(xv[c], af, poc[j]);
+      acc += norm2d(tv);
+      while (rc.nz_[j] == z) {
+        const int q = rc.take(S, j);
+        const float2 tq = f2((float)(S.lam_d * pc[j].x), (float)(S.lam_d * pc[j].y));
+        S.t2[q] = tq;
+        acc += norm2d(tq);
+      }
+    }
+    __syncthreads();
+    cur = nxt;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) { pm[j] = pc[j]; pc[j] = pnx[j]; poc[j] = pon[j]; }
+  }
+
+  const double tot = block_reduce<W>(acc, red);
+  if (tid == 0) part_d[S.slot_base + tile] = tot;
+  if (srcj >= 0) T->pa = pa_new;
+}
+
+// ---------------------------------------------------------------------------
+// fused adjoint kernel: step, r update, s = S^H r, ||s||^2 partials
+// (k < 0: the set-up pass s_0 = S^H b with a = 0)
+// ---------------------------------------------------------------------------
+
+template <int W, int RY>
+__global__ void __launch_bounds__(64 * W)
+k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_d,
+      double* __restrict__ part_s, int rhs0, int ntiles, int tiles_x, int tiles_y, int tz, int setup_only) {
+  using Ctx = TileCtx<W, RY>;
+  __shared__ float2 pl[2][Ctx::LY][Ctx::LX];
+  __shared__ double red[W + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int rl = logical / ntiles;
+  const int tile = logical - rl * ntiles;
+  const int rhs = rhs0 + rl;
+  const SysDev& S = sysv[rhs];
+  SysState* T = stv + rhs;
+  if (T->status != kActive) return;
+  const int k = T->iterB;
+  const bool setup = k < 0;
+  if (setup_only && !setup) return;
+
+  double a = 0.0;
+  if (!setup) {
+    const double gk = T->gamma[k & 1];
+    const double g0 = T->gamma0;
+    const int kt = k;
+    const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (kt >= S.max_iter);
+    if (stop) {
+      if (tile == 0 && tid == 0) {
+        T->status = (g0 == 0.0) ? kZeroRhs : ((gk <= S.rtol2 * g0) ? kConverged : kMaxIter);
+        T->iters = kt;
+      }
+      return;
+    }
+    const double dk = block_sum_slots<W>(part_d + S.slot_base, ntiles, red);
+    if (!(dk > 0.0) || !(dk <= DBL_MAX) || !(gk <= DBL_MAX)) {
+      if (tile == 0 && tid == 0) {
+        T->status = kBreakdown;
+        T->iters = kt;
+      }
+      return;
+    }
+    a = gk / dk;
+    if (tile == 0 && tid == 0) T->a[k & 1] = a;
+  }
+
+  Ctx C;
+  C.setup(S, tile, lane, w, tiles_x, tiles_y, tz);
+  const int plane = C.plane;
+  const double af = a;
+  const double w2 = S.omega_d * S.omega_d;
+  const float2* __restrict__ ro = S.r[setup ? 1 : (k & 1)];
+  float2* __restrict__ rn = S.r[setup ? 0 : ((k + 1) & 1)];
+  const float2* __restrict__ tv = S.t;
+
+  const int sxy = S.src % plane, sz = S.src / plane;
+  const int sx = sxy % S.nx, sy = sxy / S.nx;
+  int srcj = -1;
+  if (S.mode == 1 && sx == C.gx && sz >= C.z0 && sz < C.z1) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+      if (C.gy[j] == sy) srcj = j;
+  }
+
+  RecCursor<RY> rc;
+  rc.setup(S, C.gx, C.gy, C.in, C.z0);
+
+  double sxy2[RY];
+  const double sx2 = sponge_axis_d(C.gx, S.nx, S.nb, S.inv_nb_d);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
+
+  auto rval = [&](int c) -> float2 { return setup ? ro[c] : axpy2(ro[c], -af, tv[c]); };
+
+  float2 rm[RY], rc_[RY], rnx[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    rm[j] = f2(0.f, 0.f);
+    rc_[j] = f2(0.f, 0.f);
+    if (C.in[j]) {
+      const int c = C.z0 * plane + C.gy[j] * S.nx + C.gx;
+      if (C.z0 > 0) rm[j] = rval(c - plane);
+      rc_[j] = rval(c);
+    }
+    pl[0][1 + w * RY + j][1 + lane] = rc_[j];
+  }
+  for (int h = tid; h < Ctx::NH; h += 64 * W) {
+    int hx, hy;
+    Ctx::halo_xy(h, hx, hy);
+    const int xx = C.x0 + hx - 1, yy = C.y0 + hy - 1;
+    float2 v = f2(0.f, 0.f);
+    if (xx >= 0 && xx < S.nx && yy >= 0 && yy < S.ny) v = rval(C.z0 * plane + yy * S.nx + xx);
+    pl[0][hy][hx] = v;
+  }
+  __syncthreads();
+
+  double acc = 0.0;
+  double2 sa = make_double2(0.0, 0.0);
+  int cur = 0;
+  for (int z = C.z0; z < C.z1; ++z) {
+    const int nxt = cur ^ 1;
+    const bool has_next = (z + 1) < S.nz;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      rnx[j] = f2(0.f, 0.f);
+      if (C.in[j] && has_next) rnx[j] = rval((z + 1) * plane + C.gy[j] * S.nx + C.gx);
+    }
+    for (int h = tid; h < Ctx::NH; h += 64 * W) {
+      int hx, hy;
+      Ctx::halo_xy(h, hx, hy);
+      const int xx = C.x0 + hx - 1, yy = C.y0 + hy - 1;
+      float2 v = f2(0.f, 0.f);
+      if (has_next && xx >= 0 && xx < S.nx && yy >= 0 && yy < S.ny)
+        v = rval((z + 1) * plane + yy * S.nx + xx);
+      pl[nxt][hy][hx] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < RY; ++j) pl[nxt][1 + w * RY + j][1 + lane] = rnx[j];
+
+    const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      if (!C.in[j]) continue;
+      const int ly = w * RY + j;
+      const int c = z * plane + C.gy[j] * S.nx + C.gx;
+      const float2 xm = pl[cur][ly + 1][lane];
+      const float2 xp = pl[cur][ly + 1][lane + 2];
+      const float2 ym = (j > 0) ? rc_[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
+      const float2 yp = (j < RY - 1) ? rc_[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
+      const double b = S.sp_scale_d * (sxy2[j] + sz2);
+      double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], S.h2inv_d, w2 * (double)S.m[c], S.omega_d * b);
+      while (rc.nz_[j] == z) {
+        const int q = rc.take(S, j);
+        float2 r2 = S.r2[q];
+        if (!setup) {
+          r2 = axpy2(r2, -af, S.t2[q]);
+          S.r2[q] = r2;
+        }
+        sd.x += S.lam_d * r2.x;
+        sd.y += S.lam_d * r2.y;
+      }
+      const float2 s = round2(sd);
+      if (j == srcj && z == sz) {
+        sa = make_double2(-S.alpha_c * (double)rc_[j].x, -S.alpha_c * (double)rc_[j].y);
+        acc += sa.x * sa.x + sa.y * sa.y;
+      }
+      S.s[c] = s;
+      rn[c] = rc_[j];
+      acc += norm2d(s);
+    }
+    __syncthreads();
+    cur = nxt;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) { rm[j] = rc_[j]; rc_[j] = rnx[j]; }
+  }
+
+  const double tot = block_reduce<W>(acc, red);
+  if (tid == 0) part_s[S.slot_base + tile] = tot;
+  if (tile == 0 && tid == 0) T->iterA = k + 1;
+  if (srcj >= 0) T->sa = sa;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over the supported tile shapes
+// ---------------------------------------------------------------------------
+
+#define WRI_TILE_LIST(X) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(2, 8)
+
+bool cfg_supported(const TileCfg& c) {
+#define X(W_, R_) if (c.w == W_ && c.ry == R_) return c.tz >= 1;
+  WRI_TILE_LIST(X)
+#undef X
+  return false;
+}
+
+hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_s,
+                      double* part_d, int rhs0, int nrhs, int tiles_x, int tiles_y, int tiles_z,
+                      hipStream_t s) {
+  const int ntiles = tiles_x * tiles_y * tiles_z;
+  const unsigned nb = (unsigned)nrhs * (unsigned)ntiles;
+  if (nb == 0) return hipSuccess;
+#define X(W_, R_)                                                                              \
+  if (c.w == W_ && c.ry == R_) {                                                               \
+    hipLaunchKernelGGL((k_fwd<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d, \
+                       rhs0, ntiles, tiles_x, tiles_y, c.tz);                                                          \
+    return hipGetLastError();                                                                  \
+  }
+  WRI_TILE_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_d,
+                      double* part_s, int rhs0, int nrhs, int tiles_x, int tiles_y, int tiles_z,
+                      hipStream_t s, int setup_only) {
+  const int ntiles = tiles_x * tiles_y * tiles_z;
+  const unsigned nb = (unsigned)nrhs * (unsigned)ntiles;
+  if (nb == 0) return hipSuccess;
+#define X(W_, R_)                                                                              \
+  if (c.w == W_ && c.ry == R_) {                                                               \
+    hipLaunchKernelGGL((k_adj<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s, \
+                       rhs0, ntiles, tiles_x, tiles_y, c.tz, setup_only);                                                          \
+    return hipGetLastError();                                                                  \
+  }
+  WRI_TILE_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// gradient  g = sum_rhs 2 omega^2 Re(conj(u) (A u - a e)) = -sum 2 omega^2 Re(conj(u) r1)
+// and the per-block partials of ||r1||^2 for J.  Systems of one grid only.
+// ---------------------------------------------------------------------------
+
+constexpr int kGradThreads = 256;
+constexpr int kGradCells = 4;   // cells per thread
+
+int grad_blocks(int n) {
+  const int per = kGradThreads * kGradCells;
+  return (n + per - 1) / per;
+}
+
+__global__ void __launch_bounds__(kGradThreads)
+k_grad(const SysDev* __restrict__ sysv, const SysState* __restrict__ stv, int rhs0, int nrhs, int n,
+       float* __restrict__ grad, double* __restrict__ part_j, int stride, int accumulate) {
+  __shared__ double red[kGradThreads / 64 + 1];
+  const int base = blockIdx.x * (kGradThreads * kGradCells);
+  double g[kGradCells];
+#pragma unroll
+  for (int i = 0; i < kGradCells; ++i) g[i] = 0.0;
+  for (int r = 0; r < nrhs; ++r) {
+    const SysDev& S = sysv[rhs0 + r];
+    const SysState& T = stv[rhs0 + r];
+    const bool ok = T.status != kBreakdown;
+    const float2* __restrict__ r1 = S.r[T.iterA & 1];
+    const float2* __restrict__ u = S.x;
+    const double w2 = -2.0 * (double)S.omega_d * (double)S.omega_d;
+    double jj = 0.0;
+#pragma unroll
+    for (int i = 0; i < kGradCells; ++i) {
+      const int c = base + i * kGradThreads + threadIdx.x;
+      if (ok && c < n) {
+        const float2 rv = r1[c], uv = u[c];
+        g[i] += w2 * ((double)uv.x * (double)rv.x + (double)uv.y * (double)rv.y);
+        jj += norm2d(rv);
+      }
+    }
+    const double tot = block_reduce<kGradThreads / 64>(jj, red);
+    if (threadIdx.x == 0) part_j[(size_t)(rhs0 + r) * stride + blockIdx.x] = tot;
+  }
+  if (grad == nullptr) return;
+#pragma unroll
+  for (int i = 0; i < kGradCells; ++i) {
+    const int c = base + i * kGradThreads + threadIdx.x;
+    if (c < n) grad[c] = accumulate ? (float)((double)grad[c] + g[i]) : (float)g[i];
+  }
+}
+
+hipError_t launch_grad(const SysDev* sys, SysState* st, int rhs0, int nrhs, int n, float* grad,
+                       double* part_j, int stride, int accumulate, hipStream_t s) {
+  const int nb = grad_blocks(n);
+  if (nb == 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad, dim3(nb), dim3(kGradThreads), 0, s, sys, st, rhs0, nrhs, n, grad, part_j,
+                     stride, accumulate);
+  return hipGetLastError();
+}
+
+// One block per system: J = sum(part_j) + ||r2||^2, and (A u)[src] in float64.
+__global__ void __launch_bounds__(64)
+k_finalize(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_j,
+           int nparts, int stride, int rhs0) {
+  const int rhs = rhs0 + blockIdx.x;
+  const SysDev& S = sysv[rhs];
+  SysState* T = stv + rhs;
+  double v = 0.0;
+  if (part_j != nullptr)
+    for (int i = threadIdx.x; i < nparts; i += 64) v += part_j[(size_t)rhs * stride + i];
+  for (int q = threadIdx.x; q < S.n_rec; q += 64) v += norm2d(S.r2[q]);
+  v = wave_sum(v);
+  if (threadIdx.x == 0) {
+    T->J = v;
+    if (S.mode == 1) {
+      const int plane = S.nx * S.ny;
+      const int c = S.src;
+      const int z = c / plane, y = (c % plane) / S.nx, x = c % S.nx;
+      const float2* u = S.x;
+      const double2 uc = make_double2(u[c].x, u[c].y);
+      double lr = 0.0, li = 0.0;
+      auto nb = [&](bool inside, int cc) {
+        double vr = 0.0, vi = 0.0;
+        if (inside) { vr = u[cc].x; vi = u[cc].y; }
+        lr += vr - uc.x;
+        li += vi - uc.y;
+      };
+      nb(x > 0, c - 1);
+      nb(x < S.nx - 1, c + 1);
+      nb(y > 0, c - S.nx);
+      nb(y < S.ny - 1, c + S.nx);
+      nb(z > 0, c - plane);
+      nb(z < S.nz - 1, c + plane);
+      const double b = S.sp_scale_d * (sponge_axis_d(x, S.nx, S.nb, S.inv_nb_d) +
+                                       sponge_axis_d(y, S.ny, S.nb, S.inv_nb_d) +
+                                       sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d));
+      const double kre = S.omega_d * S.omega_d * (double)S.m[c];
+      const double kim = -S.omega_d * b;
+      T->alpha_ls = make_double2(lr * S.h2inv_d + kre * uc.x - kim * uc.y,
+                                 li * S.h2inv_d + kre * uc.y + kim * uc.x);
+    } else {
+      T->alpha_ls = S.alpha;
+    }
+  }
+}
+
+hipError_t launch_finalize(const SysDev* sys, SysState* st, const double* part_j, int nparts, int stride,
+                           int rhs0, int nrhs, hipStream_t s) {
+  if (nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(64), 0, s, sys, st, part_j, nparts, stride, rhs0);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_f32(float* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+hipError_t launch_zero_f32(float* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// single-operator stencil (one thread per cell; same cell arithmetic) and the
+// unfused kernels of the plain baseline
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_apply(int nx, int ny, int nz, int nbw, double h2inv, double sp_scale, double inv_nb, double omega,
+        const float* __restrict__ m, const float2* __restrict__ in, float2* __restrict__ out, int adjoint, int src,
+        double2 src_sub) {
+  const int plane = nx * ny;
+  const int n = plane * nz;
+  const double w2 = omega * omega;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int z = c / plane, rem = c - z * plane, y = rem / nx, x = rem - y * nx;
+    const float2 zero = f2(0.f, 0.f);
+    const float2 cc = in[c];
+    const float2 xm = x > 0 ? in[c - 1] : zero;
+    const float2 xp = x < nx - 1 ? in[c + 1] : zero;
+    const float2 ym = y > 0 ? in[c - nx] : zero;
+    const float2 yp = y < ny - 1 ? in[c + nx] : zero;
+    const float2 zm = z > 0 ? in[c - plane] : zero;
+    const float2 zp = z < nz - 1 ? in[c + plane] : zero;
+    const double b = sp_scale * ((sponge_axis_d(x, nx, nbw, inv_nb) + sponge_axis_d(y, ny, nbw, inv_nb)) +
+                                 sponge_axis_d(z, nz, nbw, inv_nb));
+    const double kim = adjoint ? (omega * b) : -(omega * b);
+    double2 o = helm(cc, xm, xp, ym, yp, zm, zp, h2inv, w2 * (double)m[c], kim);
+    if (c == src) { o.x -= src_sub.x; o.y -= src_sub.y; }
+    out[c] = round2(o);
+  }
+}
+
+static unsigned blocks_for(size_t n, unsigned threads = 256, unsigned cap = 65535u * 4u) {
+  size_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+hipError_t launch_apply(int nx, int ny, int nz, int nb, double h2inv, double sp_scale, double inv_nb,
+                        double omega, const float* m, const float2* in, float2* out, int adjoint, int src,
+                        double2 src_sub, hipStream_t s) {
+  const size_t n = (size_t)nx * ny * nz;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply, dim3(blocks_for(n)), dim3(256), 0, s, nx, ny, nz, nb, h2inv, sp_scale, inv_nb,
+                     omega, m, in, out, adjoint, src, src_sub);
+  return hipGetLastError();
+}
+
+__global__ void k_gather(float2* __restrict__ t2, const float2* __restrict__ p, const int* __restrict__ rec,
+                         int n_rec, double lam) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n_rec) {
+    const float2 v = p[rec[q]];
+    t2[q] = f2((float)(lam * v.x), (float)(lam * v.y));
+  }
+}
+
+hipError_t launch_gather(float2* t2, const float2* p, const int* rec, int n_rec, double lam, hipStream_t s) {
+  if (n_rec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3((n_rec + 255) / 256), dim3(256), 0, s, t2, p, rec, n_rec, lam);
+  return hipGetLastError();
+}
+
+// receiver indices are distinct within a system: no two threads touch one cell
+__global__ void k_scatter(float2* __restrict__ sv, const float2* __restrict__ r2, const int* __restrict__ rec,
+                          int n_rec, double lam) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n_rec) {
+    const int c = rec[q];
+    sv[c] = axpy2(sv[c], lam, r2[q]);
+  }
+}
+
+hipError_t launch_scatter(float2* sv, const float2* r2, const int* rec, int n_rec, double lam, hipStream_t s) {
+  if (n_rec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3((n_rec + 255) / 256), dim3(256), 0, s, sv, r2, rec, n_rec, lam);
+  return hipGetLastError();
+}
+
+constexpr int kDotThreads = 256;
+
+int dot_parts(int n) {
+  int b = (n + kDotThreads * 8 - 1) / (kDotThreads * 8);
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  return b;
+}
+
+__global__ void __launch_bounds__(kDotThreads) k_dot(const float2* __restrict__ v, int n, double* __restrict__ part) {
+  __shared__ double red[kDotThreads / 64 + 1];
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc += norm2d(v[i]);
+  const double tot = block_reduce<kDotThreads / 64>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+hipError_t launch_dot(const float2* v, int n, double* part, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(nparts), dim3(kDotThreads), 0, s, v, n, part);
+  return hipGetLastError();
+}
+
+__global__ void k_sum(const double* __restrict__ part, int nparts, double* __restrict__ out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 64) v += part[i];
+  v = wave_sum(v);
+  if (threadIdx.x == 0) *out = v;
+}
+
+hipError_t launch_sum(const double* part, int nparts, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, part, nparts, out);
+  return hipGetLastError();
+}
+
+__global__ void k_axpy(float2* __restrict__ y, const float2* __restrict__ x, double a, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    y[i] = axpy2(y[i], a, x[i]);
+}
+
+hipError_t launch_axpy(float2* y, const float2* x, double a, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n)), dim3(256), 0, s, y, x, a, n);
+  return hipGetLastError();
+}
+
+__global__ void k_xpby(float2* __restrict__ p, const float2* __restrict__ sv, double b, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = axpy2(sv[i], b, p[i]);
+}
+
+hipError_t launch_xpby(float2* p, const float2* sv, double b, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xpby, dim3(blocks_for(n)), dim3(256), 0, s, p, sv, b, n);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_f2(float2* __restrict__ d, const float2* __restrict__ sv, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) d[i] = sv[i];
+}
+
+hipError_t launch_copy_f2(float2* dst, const float2* src, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_f2, dim3(blocks_for(n)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_f2(float2* __restrict__ d, float2 v, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) d[i] = v;
+}
+
+hipError_t launch_fill_f2(float2* dst, float2 v, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f2, dim3(blocks_for(n)), dim3(256), 0, s, dst, v, n);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_f2(float2* __restrict__ d, const float2* __restrict__ sv, float a, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    d[i] = f2(a * sv[i].x, a * sv[i].y);
+}
+
+hipError_t launch_scale_f2(float2* dst, const float2* src, float a, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_f2, dim3(blocks_for(n)), dim3(256), 0, s, dst, src, a, n);
+  return hipGetLastError();
+}
+
+__global__ void k_set_state(SysState* st, int rhs, int iters, int status, double2 xa, double gamma,
+                            double gamma0) {
+  if (threadIdx.x == 0) {
+    SysState* T = st + rhs;
+    T->iters = iters;
+    T->status = status;
+    T->xa = xa;
+    T->gamma[iters & 1] = gamma;
+    T->gamma0 = gamma0;
+    T->iterA = 0;
+  }
+}
+
+hipError_t launch_set_state(SysState* st, int rhs, int iters, int status, double2 xa, double gamma,
+                            double gamma0, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, rhs, iters, status, xa, gamma, gamma0);
+  return hipGetLastError();
+}
+
+}  // namespace wri

@@ -1,0 +1,303 @@
+"""Thin ctypes binding over libwri.so (include/wri.h).
+
+Argument marshalling only: every step of the solve, the source estimate, the
+objective and the gradient runs in the library's HIP kernels.  PyTorch is used
+for device memory (workspace, wavefields, gradients) and for the current HIP
+stream.  There is no CPU fallback: if libwri.so is missing the import of the
+library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int, c_int32, c_size_t, c_void_p
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwri.so")
+
+KNOWN = 0
+ESTIMATE = 1
+FLAG_PLAIN = 1
+FLAG_NO_GRAPH = 2
+FLAG_NO_AUTOTUNE = 4
+FLAG_UNSCALED_ALPHA = 8
+FLAG_TIMING = 16
+
+
+def alpha_scale(h: float) -> float:
+    """Scale c of the source column (-c e) of S in ESTIMATE mode: sqrt(42)/h^2."""
+    return 42.0 ** 0.5 / (h * h)
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ERANGE, EDUP, ENOWS, EHIP, EBREAKDOWN = -1, -2, -3, -4, -5, -6
+SYS_CONVERGED, SYS_MAX_ITER, SYS_BREAKDOWN, SYS_ZERO_RHS = 0, 1, 2, 3
+STATUS_NAMES = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "zero_rhs"}
+
+
+class WriGrid(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("nb", c_int32),
+                ("h", c_double), ("v_ref", c_double)]
+
+
+class WriC32(ctypes.Structure):
+    _fields_ = [("re", c_float), ("im", c_float)]
+
+
+class WriC64(ctypes.Structure):
+    _fields_ = [("re", c_double), ("im", c_double)]
+
+
+class WriSystem(ctypes.Structure):
+    _fields_ = [("grid", c_int32), ("src", c_int32), ("omega", c_double), ("lambda_", c_double),
+                ("rtol", c_double), ("alpha", WriC64), ("n_rec", c_int32), ("_pad", c_int32),
+                ("rec", POINTER(c_int32)), ("d", c_void_p)]
+
+
+class WriResult(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("status", c_int32), ("relres", c_double), ("J", c_double),
+                ("alpha", WriC64), ("alpha_ls", WriC64)]
+
+
+class WriError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"wri error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libwri.so (built in-tree by paper_2410_18429_amd._build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_18429_amd._build` "
+                          f"(there is no fallback implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, pp = c_void_p, POINTER(c_void_p)
+    L.wri_workspace_bytes.argtypes = [POINTER(WriGrid), c_int32, POINTER(WriSystem), c_int32, c_int32, c_int32]
+    L.wri_workspace_bytes.restype = c_size_t
+    L.wri_validate.argtypes = [POINTER(WriGrid), c_int32, POINTER(WriSystem), c_int32, c_int32, c_int32]
+    L.wri_validate.restype = c_int
+    L.wri_solve.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32, c_int32, c_int32,
+                            c_int32, pp, POINTER(WriResult), vp, c_size_t, vp]
+    L.wri_solve.restype = c_int
+    L.wri_objective_grad.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32, c_int32,
+                                     c_int32, c_int32, POINTER(c_double), pp, pp, POINTER(WriResult), vp,
+                                     c_size_t, vp]
+    L.wri_objective_grad.restype = c_int
+    L.estimate_source.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32, c_int32,
+                                  c_int32, POINTER(WriC64), pp, POINTER(WriResult), vp, c_size_t, vp]
+    L.estimate_source.restype = c_int
+    L.wri_apply_helmholtz.argtypes = [POINTER(WriGrid), vp, c_double, vp, vp, c_int32, vp]
+    L.wri_apply_helmholtz.restype = c_int
+    L.wri_strerror.argtypes = [c_int]
+    L.wri_strerror.restype = ctypes.c_char_p
+    L.wri_last_error.argtypes = []
+    L.wri_last_error.restype = ctypes.c_char_p
+    L.wri_version.argtypes = []
+    L.wri_version.restype = c_int
+    L.wri_kernel_times.argtypes = [POINTER(c_double), POINTER(ctypes.c_int64), POINTER(c_double),
+                                   POINTER(ctypes.c_int64), POINTER(ctypes.c_int64)]
+    L.wri_kernel_times.restype = c_int
+    _lib = L
+    return L
+
+
+EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_objective_grad", "estimate_source",
+            "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version")
+
+
+def kernel_times() -> dict:
+    """Totals of the last FLAG_TIMING call on this thread."""
+    f, a = c_double(0), c_double(0)
+    nf, na, ci = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().wri_kernel_times(ctypes.byref(f), ctypes.byref(nf), ctypes.byref(a), ctypes.byref(na),
+                                  ctypes.byref(ci)))
+    return dict(fwd_ms=f.value, fwd_launches=nf.value, adj_ms=a.value, adj_launches=na.value,
+                cell_iters=ci.value)
+
+
+def last_error() -> str:
+    return lib().wri_last_error().decode()
+
+
+def _check(code: int, allow_not_converged=True) -> int:
+    if code < 0 or (code == NOT_CONVERGED and not allow_not_converged):
+        raise WriError(code, last_error() or lib().wri_strerror(code).decode())
+    return code
+
+
+def _stream(device) -> c_void_p:
+    return c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_grid(g) -> WriGrid:
+    return WriGrid(int(g.nx), int(g.ny), int(g.nz), int(g.nb), float(g.h), float(g.v_ref))
+
+
+class Batch:
+    """Device-side copy of a set of systems (a wri_synth.Problem or any object
+    with .grids, .m and .systems), plus a cached workspace.
+
+    m: per grid float32 device tensors (defaults to problem.m); d: complex64
+    device tensors per system; receiver indices stay on the host."""
+
+    def __init__(self, problem, device="cuda", m=None, mode=None):
+        self.device = torch.device(device)
+        self.problem = problem
+        mode = problem.mode if mode is None else mode
+        self.mode = {"known": KNOWN, "estimate": ESTIMATE}.get(mode, mode)
+        self.grids_py = list(problem.grids)
+        self.cgrids = (WriGrid * max(1, len(self.grids_py)))(*[make_grid(g) for g in self.grids_py])
+        src_m = problem.m if m is None else m
+        self.m = [torch.as_tensor(np.asarray(mm) if not torch.is_tensor(mm) else mm)
+                  .to(self.device, torch.float32).contiguous().reshape(-1) for mm in src_m]
+        self.rec = [np.ascontiguousarray(np.asarray(s.rec, dtype=np.int32)) for s in problem.systems]
+        self.d = [torch.as_tensor(np.asarray(s.d, dtype=np.complex64)).to(self.device).contiguous()
+                  for s in problem.systems]
+        systems = []
+        for k, s in enumerate(problem.systems):
+            a = complex(s.alpha)
+            systems.append(WriSystem(
+                int(s.grid), int(s.src), float(s.omega), float(s.lam), float(s.rtol), WriC64(a.real, a.imag),
+                int(self.rec[k].size), 0,
+                self.rec[k].ctypes.data_as(POINTER(c_int32)) if self.rec[k].size else None,
+                c_void_p(self.d[k].data_ptr()) if self.rec[k].size else None))
+        self.nsys = len(systems)
+        self.csys = (WriSystem * max(1, self.nsys))(*systems)
+        self._ws = {}
+
+    def set_m(self, m_list):
+        self.m = [mm.to(self.device, torch.float32).contiguous().reshape(-1) for mm in m_list]
+
+    def set_rtol(self, rtol):
+        r = [rtol] * self.nsys if np.isscalar(rtol) else list(rtol)
+        for k in range(self.nsys):
+            self.csys[k].rtol = float(r[k])
+
+    def m_ptrs(self):
+        return (c_void_p * max(1, len(self.m)))(*[c_void_p(t.data_ptr()) for t in self.m])
+
+    def workspace(self, mode, flags):
+        nbytes = lib().wri_workspace_bytes(self.cgrids, len(self.grids_py), self.csys, self.nsys, mode, flags)
+        if nbytes == 0:
+            raise WriError(EINVAL, last_error())
+        key = (mode, flags & FLAG_PLAIN)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def grid_cells(self, g):
+        gg = self.grids_py[g]
+        return gg.nx * gg.ny * gg.nz
+
+
+def _results(res, n):
+    return [dict(iters=res[k].iters, status=STATUS_NAMES.get(res[k].status, res[k].status),
+                 relres=res[k].relres, J=res[k].J, alpha=complex(res[k].alpha.re, res[k].alpha.im),
+                 alpha_ls=complex(res[k].alpha_ls.re, res[k].alpha_ls.im)) for k in range(n)]
+
+
+def _u_ptrs(batch: Batch, u_out):
+    if u_out is None:
+        return None
+    return (c_void_p * max(1, batch.nsys))(*[c_void_p(u.data_ptr()) if u is not None else None for u in u_out])
+
+
+def alloc_wavefields(batch: Batch) -> List[torch.Tensor]:
+    return [torch.empty(batch.grid_cells(s.grid), dtype=torch.complex64, device=batch.device)
+            for s in batch.problem.systems]
+
+
+def solve(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=None, return_u=True):
+    """Batched augmented solve. Returns (u list or None, results list)."""
+    mode = batch.mode if mode is None else mode
+    if return_u and u_out is None:
+        u_out = alloc_wavefields(batch)
+    ws = batch.workspace(mode, flags)
+    res = (WriResult * max(1, batch.nsys))()
+    code = lib().wri_solve(batch.cgrids, len(batch.grids_py), batch.m_ptrs(), batch.csys, batch.nsys, mode,
+                           int(max_iter), int(flags), _u_ptrs(batch, u_out), res, c_void_p(ws.data_ptr()),
+                           ws.numel(), _stream(batch.device))
+    _check(code)
+    return u_out, _results(res, batch.nsys)
+
+
+def objective_grad(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=None, grad_out=None):
+    """J (float), per-grid gradients (float32 device tensors), results."""
+    mode = batch.mode if mode is None else mode
+    grads = grad_out or [torch.empty(batch.grid_cells(g), dtype=torch.float32, device=batch.device)
+                         for g in range(len(batch.grids_py))]
+    gptr = (c_void_p * max(1, len(grads)))(*[c_void_p(g.data_ptr()) for g in grads])
+    ws = batch.workspace(mode, flags)
+    res = (WriResult * max(1, batch.nsys))()
+    J = c_double(0.0)
+    code = lib().wri_objective_grad(batch.cgrids, len(batch.grids_py), batch.m_ptrs(), batch.csys, batch.nsys,
+                                    mode, int(max_iter), int(flags), ctypes.byref(J), gptr,
+                                    _u_ptrs(batch, u_out), res, c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream(batch.device))
+    _check(code)
+    return J.value, grads, _results(res, batch.nsys)
+
+
+def estimate_source(batch: Batch, max_iter=20000, flags=0, u_out=None):
+    """On-the-fly source weights (complex128 numpy array) and results."""
+    ws = batch.workspace(ESTIMATE, flags)
+    res = (WriResult * max(1, batch.nsys))()
+    alpha = (WriC64 * max(1, batch.nsys))()
+    code = lib().estimate_source(batch.cgrids, len(batch.grids_py), batch.m_ptrs(), batch.csys, batch.nsys,
+                                 int(max_iter), int(flags), alpha, _u_ptrs(batch, u_out), res,
+                                 c_void_p(ws.data_ptr()), ws.numel(), _stream(batch.device))
+    _check(code)
+    return np.array([complex(alpha[k].re, alpha[k].im) for k in range(batch.nsys)]), _results(res, batch.nsys)
+
+
+def apply_helmholtz(grid, m: torch.Tensor, omega: float, x: torch.Tensor, adjoint=False) -> torch.Tensor:
+    """y = A x (or A^H x) on one grid; x complex64 device tensor of n cells."""
+    cg = make_grid(grid)
+    x = x.contiguous()
+    m = m.to(torch.float32).contiguous()
+    y = torch.empty_like(x)
+    code = lib().wri_apply_helmholtz(ctypes.byref(cg), c_void_p(m.data_ptr()), float(omega),
+                                     c_void_p(x.data_ptr()), c_void_p(y.data_ptr()), 1 if adjoint else 0,
+                                     _stream(x.device))
+    _check(code)
+    return y
+
+
+class WRIObjective(torch.autograd.Function):
+    """J(m) of the batch at model(s) m, differentiable in m.
+
+    forward runs wri_objective_grad (one batched solve); backward returns
+    grad_output * dJ/dm with no further solve (the envelope theorem: the
+    wavefield and source weight minimise J for fixed m)."""
+
+    @staticmethod
+    def forward(ctx, batch: Batch, mode, max_iter, flags, *ms):
+        batch.set_m(ms)
+        J, grads, res = objective_grad(batch, mode=mode, max_iter=max_iter, flags=flags)
+        ctx.save_for_backward(*grads)
+        ctx.shapes = [m.shape for m in ms]
+        ctx.results = res
+        batch.last_results = res
+        return torch.tensor(J, dtype=torch.float64, device=ms[0].device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        grads = ctx.saved_tensors
+        out = [(gJ.to(torch.float32) * g).reshape(s) for g, s in zip(grads, ctx.shapes)]
+        return (None, None, None, None, *out)
+
+
+def wri_objective(batch: Batch, *ms, mode=None, max_iter=20000, flags=0):
+    """Functional form of WRIObjective."""
+    return WRIObjective.apply(batch, batch.mode if mode is None else mode, max_iter, flags, *ms)

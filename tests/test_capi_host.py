@@ -1,0 +1,142 @@
+"""Host-only checks of the C ABI (no device calls): the library loads, exports
+every function declared in include/wri.h, its struct layout matches the header,
+and argument validation / workspace sizing behave as documented."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2410_18429_amd import wri
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wri.h")
+
+
+def _header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_library_exports_every_header_function():
+    L = wri.lib()
+    names = _header_functions()
+    assert set(names) == set(wri.EXPORTED), names
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.wri_version() >= 100
+
+
+def test_struct_layout_matches_header():
+    src = r"""
+    #include <stdio.h>
+    #include <stddef.h>
+    #include "wri.h"
+    int main(void) {
+      printf("%zu %zu %zu\n", sizeof(wri_grid), sizeof(wri_system), sizeof(wri_result));
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(wri_system, omega), offsetof(wri_system, lambda),
+             offsetof(wri_system, rtol), offsetof(wri_system, alpha), offsetof(wri_system, n_rec),
+             offsetof(wri_system, rec), offsetof(wri_system, d), offsetof(wri_grid, h));
+      printf("%zu %zu %zu %zu\n", offsetof(wri_result, relres), offsetof(wri_result, J),
+             offsetof(wri_result, alpha), offsetof(wri_result, alpha_ls));
+      return 0;
+    }
+    """
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split()
+    vals = list(map(int, out))
+    S, G, R = wri.WriSystem, wri.WriGrid, wri.WriResult
+    assert vals[:3] == [ctypes.sizeof(G), ctypes.sizeof(S), ctypes.sizeof(R)]
+    assert vals[3:11] == [S.omega.offset, S.lambda_.offset, S.rtol.offset, S.alpha.offset, S.n_rec.offset,
+                          S.rec.offset, S.d.offset, G.h.offset]
+    assert vals[11:] == [R.relres.offset, R.J.offset, R.alpha.offset, R.alpha_ls.offset]
+
+
+def _mk(n_rec=4, dup=False, src=5, rec_bad=False, grid=0, lam=0.1, omega=30.0, rtol=1e-6, nb=2, v_ref=1500.0):
+    g = (wri.WriGrid * 1)(wri.WriGrid(10, 9, 8, nb, 10.0, v_ref))
+    rec = np.arange(n_rec, dtype=np.int32) * 7
+    if dup and n_rec > 1:
+        rec[1] = rec[0]
+    if rec_bad:
+        rec[-1] = 10 * 9 * 8
+    fake_d = ctypes.c_void_p(0x1000)  # never dereferenced by host-only calls
+    s = (wri.WriSystem * 1)(wri.WriSystem(grid, src, omega, lam, rtol, wri.WriC64(1.0, 0.0), n_rec, 0,
+                                          rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), fake_d))
+    return g, s, rec
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({}, wri.OK),
+    (dict(dup=True), wri.EDUP),
+    (dict(rec_bad=True), wri.ERANGE),
+    (dict(src=-1), wri.ERANGE),
+    (dict(src=720), wri.ERANGE),
+    (dict(grid=1), wri.EINVAL),
+    (dict(lam=-1.0), wri.EINVAL),
+    (dict(omega=float("nan")), wri.EINVAL),
+    (dict(rtol=-1e-3), wri.EINVAL),
+    (dict(v_ref=0.0), wri.EINVAL),
+    (dict(v_ref=0.0, nb=0), wri.OK),
+    (dict(n_rec=0), wri.OK),
+])
+def test_validate_codes(kw, code):
+    g, s, rec = _mk(**kw)
+    assert wri.lib().wri_validate(g, 1, s, 1, wri.ESTIMATE, 100) == code
+    if code != wri.OK:
+        assert wri.last_error() != ""
+
+
+def test_validate_mode_and_iters():
+    g, s, rec = _mk()
+    L = wri.lib()
+    assert L.wri_validate(g, 1, s, 1, 7, 100) == wri.EINVAL
+    assert L.wri_validate(g, 1, s, 1, wri.KNOWN, -1) == wri.EINVAL
+    bad = (wri.WriGrid * 1)(wri.WriGrid(0, 9, 8, 0, 10.0, 1500.0))
+    assert L.wri_validate(bad, 1, s, 1, wri.KNOWN, 1) == wri.EINVAL
+    huge = (wri.WriGrid * 1)(wri.WriGrid(2048, 2048, 512, 0, 10.0, 1500.0))
+    assert L.wri_validate(huge, 1, None, 0, wri.KNOWN, 1) == wri.EINVAL
+
+
+def test_workspace_bytes_and_dedup():
+    L = wri.lib()
+    g, s, rec = _mk()
+    one = L.wri_workspace_bytes(g, 1, s, 1, wri.ESTIMATE, 0)
+    assert one > 7 * 8 * 720
+    two = (wri.WriSystem * 2)(s[0], s[0])
+    both = L.wri_workspace_bytes(g, 1, two, 2, wri.ESTIMATE, 0)
+    assert one < both < 2 * one + 4096
+    plain = L.wri_workspace_bytes(g, 1, two, 2, wri.ESTIMATE, wri.FLAG_PLAIN)
+    assert plain < both
+    gb, sb, _ = _mk(dup=True)
+    assert L.wri_workspace_bytes(gb, 1, sb, 1, wri.ESTIMATE, 0) == 0
+
+
+def test_solve_rejects_small_workspace_before_any_device_call():
+    L = wri.lib()
+    g, s, rec = _mk()
+    res = (wri.WriResult * 1)()
+    m = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x2000))
+    code = L.wri_solve(g, 1, m, s, 1, wri.ESTIMATE, 10, 0, None, res, ctypes.c_void_p(0x3000), 16, None)
+    assert code == wri.ENOWS
+    assert "workspace" in wri.last_error()
+    code = L.wri_solve(g, 1, m, s, 1, wri.ESTIMATE, 10, 0, None, None, ctypes.c_void_p(0x3000), 1 << 40, None)
+    assert code == wri.EINVAL
+    g2, s2, _ = _mk(dup=True)
+    code = L.wri_solve(g2, 1, m, s2, 1, wri.ESTIMATE, 10, 0, None, res, ctypes.c_void_p(0x3000), 1 << 40, None)
+    assert code == wri.EDUP
+
+
+def test_strerror():
+    L = wri.lib()
+    for c in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert len(L.wri_strerror(c)) > 0

@@ -1,0 +1,333 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (float32 vectors, float64 scalars):
+  operator application  |y - y_ref| <= 1e-5 max|y_ref| element-wise
+  CGLS iterates after k steps vs the oracle's complex128 CGLS: rel 1e-4
+  converged solves (parity rtol 1e-8) vs the exact minimiser: u, alpha, J rel 1e-4
+  gradient rel 1e-3 (lambda = 12/h^2)
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import wri_synth
+from paper_2410_18429_amd import wri
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.init()
+    yield
+    torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# operator
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("adjoint", [0, 1])
+@pytest.mark.parametrize("shape", [(70, 37, 19), (5, 3, 66), (1, 1, 9)])
+def test_apply_helmholtz_matches_oracle(shape, adjoint):
+    _say(f"apply shape={shape} adjoint={adjoint}")
+    g = wri_synth.Grid(*shape, h=12.5, nb=min(3, max(0, min(shape) // 2 - 1)), v_ref=1600.0)
+    rng = np.random.default_rng(1)
+    m = rng.uniform(1 / 4000.0 ** 2, 1 / 1500.0 ** 2, g.n)
+    x = (rng.standard_normal(g.n) + 1j * rng.standard_normal(g.n)).astype(np.complex64)
+    om = 2 * np.pi * 7.0
+    A = oracle.helmholtz(g, m.astype(np.float32).astype(np.float64), om)
+    if adjoint:
+        A = A.conj().T
+    ref = A @ x.astype(np.complex128)
+    y = wri.apply_helmholtz(g, torch.tensor(m, dtype=torch.float32, device=DEV), om,
+                            torch.tensor(x, device=DEV), adjoint=bool(adjoint))
+    err = np.abs(_np(y) - ref).max() / np.abs(ref).max()
+    assert err <= 1e-5, err
+
+
+# --------------------------------------------------------------------------
+# fused CGLS iterates vs the oracle's reference CGLS
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+@pytest.mark.parametrize("k", [1, 2, 7])
+def test_fused_iterates_match_reference_cgls(mode, k):
+    _say(f"iterates mode={mode} k={k}")
+    p = wri_synth.custom_problem((70, 37, 19), nb=3, n_src=2, n_rec=12, seed=21, freqs=(7.0,), rtol=0.0)
+    b = wri.Batch(p, device=DEV, mode=mode)
+    u, res = wri.solve(b, max_iter=k, flags=wri.FLAG_NO_AUTOTUNE)
+    for i, s in enumerate(p.systems):
+        A, P, e = oracle.system_operators(p, i)
+        ref = oracle.cgls(A, P, s.lam, s.src, mode, s.alpha, s.d.astype(np.complex64).astype(np.complex128),
+                          rtol=0.0, maxiter=k, alpha_scale=wri.alpha_scale(p.grids[0].h))
+        assert res[i]["iters"] == k and res[i]["status"] == "max_iter"
+        assert rel(_np(u[i]), ref["u"]) < 1e-4
+        assert abs(res[i]["relres"] - ref["relres"]) < 1e-4 * ref["relres"]
+        if mode == "estimate":
+            assert abs(res[i]["alpha"] - ref["alpha"]) < 1e-4 * abs(ref["alpha"])
+
+
+# --------------------------------------------------------------------------
+# converged solves vs the exact minimiser
+# --------------------------------------------------------------------------
+
+SHAPES = [(16, 16, 16), (70, 37, 19), (33, 65, 12), (5, 6, 7)]
+
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_solve_parity_exact(shape, mode):
+    _say(f"solve shape={shape} mode={mode}")
+    p = wri_synth.custom_problem(shape, nb=min(3, min(shape) // 3), n_src=2, n_rec=10, seed=7,
+                                 freqs=(6.0, 9.0), rtol=1e-8)
+    ref = oracle.objective_grad(p, mode=mode)
+    b = wri.Batch(p, device=DEV, mode=mode)
+    J, grads, res = wri.objective_grad(b)
+    u, res_u = wri.solve(b)
+    for i in range(len(p.systems)):
+        assert res[i]["status"] == "converged", res[i]
+        assert rel(_np(u[i]), ref["u"][i]) < 1e-4
+        if mode == "estimate":
+            assert abs(res_u[i]["alpha_ls"] - ref["alpha"][i]) < 1e-4 * abs(ref["alpha"][i])
+            assert abs(res_u[i]["alpha"] - ref["alpha"][i]) < 1e-4 * abs(ref["alpha"][i])
+        assert abs(res[i]["J"] - ref["J_sys"][i]) < 1e-4 * ref["J_sys"][i]
+    assert abs(J - ref["J"]) < 1e-4 * ref["J"]
+    g = grads[0].cpu().numpy().astype(np.float64)
+    assert rel(g, ref["g"][0].reshape(-1)) < 1e-3
+
+
+def test_tiny_config_both_modes():
+    _say("tiny config")
+    p = wri_synth.make_config("tiny", data="none")
+    p = p.with_data(oracle.observed_data(p, seed=0))
+    for mode in ("estimate", "known"):
+        ref = oracle.objective_grad(p, mode=mode)
+        b = wri.Batch(p, device=DEV, mode=mode)
+        b.set_rtol(1e-9)
+        J, grads, res = wri.objective_grad(b)
+        u, _ = wri.solve(b)
+        assert rel(_np(u[0]), ref["u"][0]) < 1e-4
+        assert abs(J - ref["J"]) < 1e-4 * ref["J"]
+        assert rel(grads[0].cpu().numpy(), ref["g"][0].reshape(-1)) < 1e-3
+
+
+# --------------------------------------------------------------------------
+# batching
+# --------------------------------------------------------------------------
+
+def test_batched_equals_single_bitwise():
+    _say("batched vs single")
+    p = wri_synth.custom_problem((40, 30, 20), nb=3, n_src=3, n_rec=9, seed=8, freqs=(5.0, 8.0), rtol=1e-6)
+    ub, rb = wri.solve(wri.Batch(p, device=DEV))
+    for i in range(len(p.systems)):
+        us, rs = wri.solve(wri.Batch(p.subset([i]), device=DEV))
+        assert rs[0]["iters"] == rb[i]["iters"]
+        assert torch.equal(us[0], ub[i])
+
+
+def test_plain_path_matches_batched_and_oracle():
+    _say("plain vs batched")
+    p = wri_synth.custom_problem((24, 22, 20), nb=3, n_src=2, n_rec=9, seed=9, freqs=(6.0,), rtol=1e-8)
+    ref = oracle.objective_grad(p)
+    b = wri.Batch(p, device=DEV)
+    Jp, gp, rp = wri.objective_grad(b, flags=wri.FLAG_PLAIN)
+    up, _ = wri.solve(b, flags=wri.FLAG_PLAIN)
+    Jb, gb, rb = wri.objective_grad(b)
+    for i in range(len(p.systems)):
+        assert rp[i]["status"] == "converged"
+        assert rel(_np(up[i]), ref["u"][i]) < 1e-4
+        assert abs(rp[i]["iters"] - rb[i]["iters"]) <= max(3, 0.05 * rb[i]["iters"])
+    assert abs(Jp - ref["J"]) < 1e-4 * ref["J"]
+    assert rel(gp[0].cpu().numpy(), ref["g"][0].reshape(-1)) < 1e-3
+
+
+def test_graph_and_eager_agree():
+    _say("graph vs eager")
+    p = wri_synth.custom_problem((40, 20, 30), nb=3, n_src=2, n_rec=8, seed=10, freqs=(7.0,), rtol=1e-6)
+    b = wri.Batch(p, device=DEV)
+    ug, rg = wri.solve(b)
+    ue, re_ = wri.solve(b, flags=wri.FLAG_NO_GRAPH)
+    ug2, rg2 = wri.solve(b)          # replay of the cached graph
+    for i in range(len(p.systems)):
+        assert torch.equal(ug[i], ue[i]) and torch.equal(ug[i], ug2[i])
+        assert rg[i]["iters"] == re_[i]["iters"] == rg2[i]["iters"]
+
+
+def _uneven_problem():
+    """Three grids of different sizes in one batch, per-system tolerances."""
+    rng = np.random.default_rng(11)
+    parts = [wri_synth.custom_problem(sh, h=h, nb=3, n_src=2, n_rec=8, seed=s, freqs=(f,), rtol=1e-6)
+             for sh, h, s, f in (((16, 16, 16), 20.0, 1, 5.0), ((24, 20, 18), 14.0, 2, 8.0),
+                                  ((33, 17, 9), 10.0, 3, 12.0))]
+    grids, m, mt, systems = [], [], [], []
+    for gi, q in enumerate(parts):
+        grids += q.grids
+        m += q.m
+        mt += q.m_true
+        for s in q.systems:
+            s.grid = gi
+            s.rtol = float(10.0 ** (-2 - 4 * rng.uniform()))
+            systems.append(s)
+    return wri_synth.Problem("uneven-small", grids, m, mt, systems)
+
+
+def test_uneven_grids_adaptive_tolerances():
+    _say("uneven grids")
+    p = _uneven_problem()
+    b = wri.Batch(p, device=DEV)
+    u, res = wri.solve(b)
+    iters = [r["iters"] for r in res]
+    assert len(set(iters)) > 1
+    for i, s in enumerate(p.systems):
+        A, P, e = oracle.system_operators(p, i)
+        ref = oracle.cgls(A, P, s.lam, s.src, "estimate", 0, s.d.astype(np.complex64).astype(np.complex128),
+                          rtol=s.rtol, maxiter=100000, alpha_scale=wri.alpha_scale(p.grids[s.grid].h))
+        assert res[i]["status"] == "converged" and res[i]["relres"] <= s.rtol
+        assert abs(res[i]["iters"] - ref["iters"]) <= max(2, 0.1 * ref["iters"]), (res[i]["iters"], ref["iters"])
+        # float64 true normal residual of the GPU iterate, against the floor set
+        # by storing the exact minimiser in complex64
+        tr = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d, _np(u[i]), res[i]["alpha"])
+        ue, ae = oracle.solve_estimate(A, P, s.lam, s.src, s.d)
+        floor = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d,
+                                       ue.astype(np.complex64).astype(np.complex128), ae)
+        assert tr <= 2 * s.rtol + 3 * floor, (tr, s.rtol, floor)
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+
+def test_zero_data_gives_zero_solution():
+    _say("zero rhs")
+    p = wri_synth.custom_problem((20, 10, 8), nb=2, n_src=2, n_rec=5, seed=12)
+    p = p.with_data([np.zeros_like(s.d) for s in p.systems])
+    b = wri.Batch(p, device=DEV)
+    J, g, res = wri.objective_grad(b)
+    u, _ = wri.solve(b)
+    for i in range(len(p.systems)):
+        assert res[i]["status"] == "zero_rhs" and res[i]["iters"] == 0
+        assert not torch.any(u[i] != 0)
+    assert J == 0.0 and not torch.any(g[0] != 0)
+
+
+def test_max_iter_zero():
+    _say("max_iter 0")
+    p = wri_synth.custom_problem((20, 10, 8), nb=2, n_src=1, n_rec=5, seed=13)
+    u, res = wri.solve(wri.Batch(p, device=DEV), max_iter=0)
+    assert res[0]["status"] == "max_iter" and res[0]["iters"] == 0
+    assert not torch.any(u[0] != 0)
+
+
+def test_known_mode_without_receivers_is_plain_helmholtz():
+    _say("no receivers")
+    p = wri_synth.custom_problem((18, 12, 10), nb=2, n_src=1, n_rec=4, seed=14, rtol=1e-9)
+    s = p.systems[0]
+    s.rec = np.zeros(0, np.int32)
+    s.d = np.zeros(0, complex)
+    A, P, e = oracle.system_operators(p, 0)
+    uref = oracle.plain_helmholtz_solution(A, s.alpha * e)
+    u, res = wri.solve(wri.Batch(p, device=DEV, mode="known"))
+    assert res[0]["status"] == "converged"
+    assert rel(_np(u[0]), uref) < 1e-4
+
+
+def test_corner_sources_and_receiver_on_source():
+    _say("corner sources")
+    p = wri_synth.custom_problem((13, 7, 5), nb=1, n_src=2, n_rec=5, seed=15, rtol=1e-9)
+    g = p.grids[0]
+    p.systems[0].src = 0
+    p.systems[1].src = g.n - 1
+    p.systems[1].rec = np.unique(np.concatenate([p.systems[1].rec, [g.n - 1, 0]])).astype(np.int32)
+    rng = np.random.default_rng(0)
+    p.systems[1].d = rng.standard_normal(p.systems[1].rec.size) * 1e-3 + 0j
+    for mode in ("estimate", "known"):
+        ref = oracle.objective_grad(p, mode=mode)
+        u, res = wri.solve(wri.Batch(p, device=DEV, mode=mode))
+        for i in range(2):
+            assert rel(_np(u[i]), ref["u"][i]) < 1e-4, (mode, i)
+
+
+@pytest.mark.parametrize("shape", [(3, 2, 1), (1, 1, 5), (64, 1, 3), (65, 17, 2)])
+def test_degenerate_grids(shape):
+    _say(f"degenerate {shape}")
+    p = wri_synth.custom_problem(shape, nb=0, n_src=1, n_rec=min(3, shape[2]), seed=16, rtol=1e-9)
+    ref = oracle.objective_grad(p)
+    u, res = wri.solve(wri.Batch(p, device=DEV))
+    assert res[0]["status"] in ("converged",)
+    assert rel(_np(u[0]), ref["u"][0]) < 1e-4
+
+
+def test_nan_model_reports_breakdown():
+    _say("nan model")
+    p = wri_synth.custom_problem((20, 10, 8), nb=2, n_src=2, n_rec=5, seed=17)
+    p.m[0] = p.m[0].copy()
+    p.m[0][3, 4, 5] = np.nan
+    with pytest.raises(wri.WriError) as ei:
+        wri.solve(wri.Batch(p, device=DEV))
+    assert ei.value.code == wri.EBREAKDOWN
+
+
+# --------------------------------------------------------------------------
+# differentiation: autograd and the 32^3 crop of the 128^3 workload
+# --------------------------------------------------------------------------
+
+def test_autograd_function_composes():
+    _say("autograd")
+    p = wri_synth.custom_problem((24, 20, 16), nb=3, n_src=2, n_rec=8, seed=18, freqs=(6.0,), rtol=1e-9)
+    b = wri.Batch(p, device=DEV)
+    m = torch.tensor(p.m[0], dtype=torch.float32, device=DEV, requires_grad=True)
+    J = wri.wri_objective(b, m)
+    loss = 3.0 * J + (m.double() ** 2).sum()
+    loss.backward()
+    Jr, gr, _ = wri.objective_grad(b)
+    g_expect = 3.0 * gr[0].reshape(m.shape) + 2.0 * m.detach()
+    assert abs(J.item() - Jr) <= 1e-12 * abs(Jr)
+    assert torch.allclose(m.grad, g_expect, rtol=1e-5, atol=1e-5 * g_expect.abs().max().item())
+    # directional finite difference of the GPU objective
+    rng = np.random.default_rng(5)
+    dm = torch.tensor(rng.standard_normal(p.m[0].shape) * p.m[0] * 1e-2, dtype=torch.float32, device=DEV)
+    h = 0.5
+    Jp = wri.wri_objective(b, m.detach() + h * dm).item()
+    Jm = wri.wri_objective(b, m.detach() - h * dm).item()
+    fd = (Jp - Jm) / (2 * h)
+    an = float((gr[0].reshape(m.shape).double() * dm.double()).sum())
+    assert abs(fd - an) < 2e-2 * abs(an), (fd, an)
+
+
+def test_crop32_gradient_matches_golden():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "crop32_oracle.npz")
+    gold = np.load(path)
+    _say("crop32 golden")
+    p = wri_synth.make_config("crop32", seed=0)
+    b = wri.Batch(p, device=DEV)
+    J, grads, res = wri.objective_grad(b)
+    assert all(r["status"] == "converged" for r in res)
+    g = grads[0].cpu().numpy().astype(np.float64)
+    _say(f"crop32 J err {abs(J - float(gold['J'])) / float(gold['J']):.2e}  g err {rel(g, gold['g'].reshape(-1)):.2e}")
+    assert abs(J - float(gold["J"])) < 1e-4 * float(gold["J"])
+    alpha = np.array([r["alpha_ls"] for r in res])
+    assert np.max(np.abs(alpha - gold["alpha"]) / np.abs(gold["alpha"])) < 1e-4
+    assert rel(g, gold["g"].reshape(-1)) < 1e-3

@@ -424,3 +424,16 @@ def test_paper_source_tables():
     af = np.array([complex(*z) for z in cam["alpha_final"]])
     atp = np.array([complex(*z) for z in cam["alpha_true"]])
     assert abs(100 * np.linalg.norm(af - atp) / np.linalg.norm(atp) - cam["rel_err_final_pct"]) < 0.15
+
+
+def test_cgls_column_scaling_keeps_minimiser():
+    """Scaling the source column of S (-c e, unknown alpha/c) is a right
+    diagonal preconditioner: the converged (u, alpha) must not depend on c."""
+    p = wri_synth.custom_problem((8, 7, 6), nb=2, n_src=1, n_rec=6, seed=19, lam=0.12)
+    s = p.systems[0]
+    A, P, e = oracle.system_operators(p, 0)
+    u, a = oracle.solve_estimate(A, P, s.lam, s.src, s.d)
+    for c in (1.0, 42 ** 0.5 / p.grids[0].h ** 2, 7.0):
+        out = oracle.cgls(A, P, s.lam, s.src, "estimate", 0, s.d, rtol=1e-12, maxiter=100000, alpha_scale=c)
+        assert np.linalg.norm(out["u"] - u) / np.linalg.norm(u) < 1e-8
+        assert abs(out["alpha"] - a) / abs(a) < 1e-8
