@@ -109,7 +109,7 @@ enum { WRI_KNOWN = 0, WRI_ESTIMATE = 1 };
 
 enum {
   WRI_OK = 0,
-  WRI_NOT_CONVERGED = 1,
+  WRI_NOT_CONVERGED = 1,   /* some system stopped at max_iter or diverged          */
   WRI_EINVAL = -1,      /* bad argument (null pointer, size, mode, ...)       */
   WRI_ERANGE = -2,      /* a cell index (src or receiver) outside its grid    */
   WRI_EDUP = -3,        /* duplicate receiver indices within one system       */
@@ -122,7 +122,10 @@ enum {
   WRI_SYS_CONVERGED = 0,
   WRI_SYS_MAX_ITER = 1,
   WRI_SYS_BREAKDOWN = 2,
-  WRI_SYS_ZERO_RHS = 3   /* S^H b = 0: the solution is x = 0, no iteration   */
+  WRI_SYS_ZERO_RHS = 3,  /* S^H b = 0: the solution is x = 0, no iteration   */
+  WRI_SYS_DIVERGED = 4   /* ||S^H r_k|| rose 1e4x above its running minimum: the
+                            tolerance is below what float32 storage resolves;
+                            the last iterate is returned                       */
 };
 
 /* flags (bitwise OR) */

@@ -808,7 +808,7 @@ int solve_common(const wri_grid* grids, int32_t n_grids, const float* const* m, 
     if (alpha_out) alpha_out[i] = r.alpha_ls;
     J += T.J;
     if (T.status == kBreakdown) ret = WRI_EBREAKDOWN;
-    else if (T.status == kMaxIter && ret == WRI_OK) ret = WRI_NOT_CONVERGED;
+    else if ((T.status == kMaxIter || T.status == kDiverged) && ret == WRI_OK) ret = WRI_NOT_CONVERGED;
   }
   if (J_out) *J_out = J;
   if (ret == WRI_EBREAKDOWN) fail(WRI_EBREAKDOWN, "at least one system broke down (non-finite or non-positive curvature)");

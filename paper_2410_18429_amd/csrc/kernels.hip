@@ -149,6 +149,7 @@ __global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, S
     if (threadIdx.x == 0) {
       SysState* T = stv + rhs;
       T->gamma[0] = T->gamma[1] = 0.0;
+      T->gmin[0] = T->gmin[1] = 0.0;
       T->gamma0 = 0.0;
       T->a[0] = T->a[1] = 0.0;
       T->xa = make_double2(0.0, 0.0);
@@ -260,11 +261,13 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
 
   const double gk = block_sum_slots<W>(part_s + S.slot_base, ntiles, red);
   const double g0 = (k == 0) ? gk : T->gamma0;
-  const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter);
+  const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
+  const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
   const double beta = (k == 0) ? 0.0 : gk / T->gamma[(k - 1) & 1];
   const double aprev = (k == 0) ? 0.0 : T->a[(k - 1) & 1];
   if (tile == 0 && tid == 0) {
     T->gamma[k & 1] = gk;
+    T->gmin[k & 1] = fmin(gmin, gk);
     if (k == 0) T->gamma0 = gk;
     T->iterB = k;
   }
@@ -449,12 +452,14 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   if (!setup) {
     const double gk = T->gamma[k & 1];
     const double g0 = T->gamma0;
-    const int kt = k;
-    const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (kt >= S.max_iter);
+    const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
+    const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
     if (stop) {
       if (tile == 0 && tid == 0) {
-        T->status = (g0 == 0.0) ? kZeroRhs : ((gk <= S.rtol2 * g0) ? kConverged : kMaxIter);
-        T->iters = kt;
+        T->status = (g0 == 0.0) ? kZeroRhs
+                  : (gk <= S.rtol2 * g0) ? kConverged
+                  : (gk > kDivergeRatio * gmin) ? kDiverged : kMaxIter;
+        T->iters = k;
       }
       return;
     }
@@ -462,7 +467,7 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
     if (!(dk > 0.0) || !(dk <= DBL_MAX) || !(gk <= DBL_MAX)) {
       if (tile == 0 && tid == 0) {
         T->status = kBreakdown;
-        T->iters = kt;
+        T->iters = k;
       }
       return;
     }

@@ -14,7 +14,11 @@ constexpr int kTX = 64;
 constexpr int kXCD = 8;
 
 // Per-system status while iterating (final values mirror WRI_SYS_*).
-enum : int { kActive = -1, kConverged = 0, kMaxIter = 1, kBreakdown = 2, kZeroRhs = 3 };
+enum : int { kActive = -1, kConverged = 0, kMaxIter = 1, kBreakdown = 2, kZeroRhs = 3, kDiverged = 4 };
+// The recurred ||S^H r_k||^2 growing this far above its running minimum means
+// the float32 recurrences have lost the solution (tolerance below what the
+// storage precision can resolve): stop instead of iterating on noise.
+constexpr double kDivergeRatio = 1e8;
 
 // Read-only description of one right-hand side, resident in device memory.
 // All vectors of one system live on that system's grid (n = nx*ny*nz cells,
@@ -54,6 +58,7 @@ struct SysDev {
 struct SysState {
   double gamma[2];    // ||s_k||^2 by iteration parity (written by the forward kernel)
   double gamma0;
+  double gmin[2];     // running minimum of gamma by parity (written by the forward kernel)
   double a[2];        // step gamma_k / ||t_k||^2 by parity (written by the adjoint kernel)
   double2 xa, pa, sa; // source-weight components of x, p, s (ESTIMATE)
   double J;           // objective share of this system

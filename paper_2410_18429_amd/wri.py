@@ -34,8 +34,8 @@ def alpha_scale(h: float) -> float:
 
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ERANGE, EDUP, ENOWS, EHIP, EBREAKDOWN = -1, -2, -3, -4, -5, -6
-SYS_CONVERGED, SYS_MAX_ITER, SYS_BREAKDOWN, SYS_ZERO_RHS = 0, 1, 2, 3
-STATUS_NAMES = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "zero_rhs"}
+SYS_CONVERGED, SYS_MAX_ITER, SYS_BREAKDOWN, SYS_ZERO_RHS, SYS_DIVERGED = 0, 1, 2, 3, 4
+STATUS_NAMES = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "zero_rhs", 4: "diverged"}
 
 
 class WriGrid(ctypes.Structure):
