@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -53,8 +54,10 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Slab-tile candidates explored by the autotuner; the first is the default.
 const TileCfg kCands[] = {
-    {4, 4, 32}, {4, 4, 16}, {4, 4, 64}, {4, 2, 32}, {4, 2, 16}, {4, 2, 64},
-    {8, 2, 32}, {8, 2, 16}, {2, 8, 32}, {4, 1, 32}, {8, 1, 32}, {8, 1, 16},
+    {4, 4, 32, 0}, {4, 4, 16, 0}, {4, 4, 64, 0}, {4, 2, 32, 0}, {4, 2, 16, 0}, {4, 2, 64, 0},
+    {8, 2, 32, 0}, {8, 2, 16, 0}, {2, 8, 32, 0}, {4, 1, 32, 0}, {8, 1, 32, 0}, {8, 1, 16, 0},
+    {4, 4, 32, 1}, {4, 2, 32, 1}, {4, 2, 64, 1}, {8, 2, 32, 1}, {8, 1, 32, 1}, {8, 1, 64, 1},
+    {4, 1, 64, 1}, {8, 2, 64, 1},
 };
 constexpr int kNumCands = sizeof(kCands) / sizeof(kCands[0]);
 
@@ -436,8 +439,32 @@ int launch_setup(Ctx& C, int only_group = -1) {
   return WRI_OK;
 }
 
+bool verbose() {
+  static const bool v = [] { const char* e = getenv("WRI_VERBOSE"); return e && *e && *e != '0'; }();
+  return v;
+}
+
+// WRI_TILE="w,ry,tz,pf" forces one of the candidate tiles (tests, experiments)
+bool forced_tile(TileCfg* out) {
+  const char* e = getenv("WRI_TILE");
+  if (e == nullptr || *e == 0) return false;
+  TileCfg t{0, 0, 0, 0};
+  if (sscanf(e, "%d,%d,%d,%d", &t.w, &t.ry, &t.tz, &t.pf) != 4) return false;
+  for (int i = 0; i < kNumCands; ++i)
+    if (kCands[i].w == t.w && kCands[i].ry == t.ry && kCands[i].tz == t.tz && kCands[i].pf == t.pf) {
+      *out = t;
+      return true;
+    }
+  return false;
+}
+
 // time a few iterations of one group per candidate tile; keep the fastest
 int autotune(Ctx& C) {
+  TileCfg forced;
+  if (forced_tile(&forced)) {
+    for (size_t gi = 0; gi < C.groups.size(); ++gi) C.tiling[gi] = make_tiling(forced, C.grids[C.groups[gi].grid]);
+    return WRI_OK;
+  }
   for (size_t gi = 0; gi < C.groups.size(); ++gi) {
     const Group& G = C.groups[gi];
     const wri_grid& g = C.grids[G.grid];
@@ -474,6 +501,9 @@ int autotune(Ctx& C) {
       WRI_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       WRI_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (verbose())
+        fprintf(stderr, "[wri] autotune grid %dx%dx%d nrhs %d: w=%d ry=%d tz=%d pf=%d -> %.3f ms / 3 iterations\n",
+                g.nx, g.ny, g.nz, G.nrhs, kCands[c].w, kCands[c].ry, kCands[c].tz, kCands[c].pf, ms);
       if (ms < best) { best = ms; best_cfg = kCands[c]; }
     }
     (void)hipEventDestroy(e0);
@@ -491,8 +521,8 @@ std::string graph_key(const Ctx& C, int chunk) {
   k += buf;
   for (size_t gi = 0; gi < C.groups.size(); ++gi) {
     const Tiling& t = C.tiling[gi];
-    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d,%d,%d;", C.groups[gi].rhs0, C.groups[gi].nrhs, t.cfg.w, t.cfg.ry,
-             t.cfg.tz, t.tx, t.ty, t.tz);
+    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d,%d,%d,%d;", C.groups[gi].rhs0, C.groups[gi].nrhs, t.cfg.w,
+             t.cfg.ry, t.cfg.tz, t.cfg.pf, t.tx, t.ty, t.tz);
     k += buf;
   }
   return k;
@@ -557,10 +587,18 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     WRI_HIP(hipMemcpyAsync(C.dsys, C.hsys.data(), sizeof(SysDev) * C.n_sys, hipMemcpyHostToDevice, C.st));
     int rc = upload_receivers(C);
     if (rc != WRI_OK) return rc;
-    if (!(C.flags & WRI_FLAG_NO_AUTOTUNE)) {
+    TileCfg forced;
+    if (forced_tile(&forced)) {
+      for (size_t gi = 0; gi < C.groups.size(); ++gi) C.tiling[gi] = make_tiling(forced, C.grids[C.groups[gi].grid]);
+    } else if (!(C.flags & WRI_FLAG_NO_AUTOTUNE)) {
       rc = autotune(C);
       if (rc != WRI_OK) return rc;
     }
+    if (verbose())
+      for (size_t gi = 0; gi < C.groups.size(); ++gi)
+        fprintf(stderr, "[wri] grid %d (%d systems): tile w=%d ry=%d tz=%d pf=%d, %d tiles per system\n",
+                C.groups[gi].grid, C.groups[gi].nrhs, C.tiling[gi].cfg.w, C.tiling[gi].cfg.ry, C.tiling[gi].cfg.tz,
+                C.tiling[gi].cfg.pf, C.tiling[gi].ntiles());
     rc = launch_setup(C);
     if (rc != WRI_OK) return rc;
     const bool timing = (C.flags & WRI_FLAG_TIMING) != 0;

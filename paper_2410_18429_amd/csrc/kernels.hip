@@ -592,13 +592,453 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
 }
 
 // ---------------------------------------------------------------------------
+// Software-pipelined variants (same arithmetic, same outputs bit for bit):
+// while plane z is computed, the raw inputs of plane z+2 are already in
+// flight and plane z+1 waits complete in LDS, so a wavefront no longer stalls
+// on the loads it is about to use.  LDS holds three planes (z, z+1, z+2).
+// ---------------------------------------------------------------------------
+
+template <int W, int RY>
+__global__ void __launch_bounds__(64 * W)
+k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_s,
+         double* __restrict__ part_d, int rhs0, int ntiles, int tiles_x, int tiles_y, int tz) {
+  using Ctx = TileCtx<W, RY>;
+  constexpr int NT = 64 * W;
+  constexpr int HS = (Ctx::NH + NT - 1) / NT;  // halo slots per thread
+  __shared__ float2 pl[3][Ctx::LY][Ctx::LX];
+  __shared__ double red[W + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int rl = logical / ntiles;
+  const int tile = logical - rl * ntiles;
+  const int rhs = rhs0 + rl;
+  const SysDev& S = sysv[rhs];
+  SysState* T = stv + rhs;
+  if (T->status != kActive) return;
+  const int k = T->iterA;
+
+  const double gk = block_sum_slots<W>(part_s + S.slot_base, ntiles, red);
+  const double g0 = (k == 0) ? gk : T->gamma0;
+  const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
+  const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
+  const double beta = (k == 0) ? 0.0 : gk / T->gamma[(k - 1) & 1];
+  const double aprev = (k == 0) ? 0.0 : T->a[(k - 1) & 1];
+  if (tile == 0 && tid == 0) {
+    T->gamma[k & 1] = gk;
+    T->gmin[k & 1] = fmin(gmin, gk);
+    if (k == 0) T->gamma0 = gk;
+    T->iterB = k;
+  }
+
+  Ctx C;
+  C.setup(S, tile, lane, w, tiles_x, tiles_y, tz);
+  const int plane = C.plane;
+  const double af = aprev, bf = beta;
+  const double w2 = S.omega_d * S.omega_d;
+  const float2* __restrict__ sv = S.s;
+  const float2* __restrict__ po = S.p[k & 1];
+  float2* __restrict__ pn = S.p[(k + 1) & 1];
+  float2* __restrict__ xv = S.x;
+  const float* __restrict__ mv = S.m;
+
+  const int sxy = S.src % plane, sz = S.src / plane;
+  const int sx = sxy % S.nx, sy = sxy / S.nx;
+  int srcj = -1;
+  if (S.mode == 1 && sx == C.gx && sz >= C.z0 && sz < C.z1) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+      if (C.gy[j] == sy) srcj = j;
+  }
+
+  if (stop) {
+    if (aprev != 0.0) {
+      for (int z = C.z0; z < C.z1; ++z) {
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+          if (!C.in[j]) continue;
+          const int c = z * plane + C.gy[j] * S.nx + C.gx;
+          xv[c] = axpy2(xv[c], af, po[c]);
+        }
+      }
+      if (srcj >= 0) {
+        const double2 pa = T->pa;
+        T->xa = make_double2(T->xa.x + aprev * pa.x, T->xa.y + aprev * pa.y);
+      }
+    }
+    return;
+  }
+
+  double2 pa_new = make_double2(0.0, 0.0);
+  if (srcj >= 0) {
+    const double2 pa = T->pa, sa = T->sa;
+    pa_new = make_double2(sa.x + beta * pa.x, sa.y + beta * pa.y);
+    T->xa = make_double2(T->xa.x + aprev * pa.x, T->xa.y + aprev * pa.y);
+  }
+
+  RecCursor<RY> rc;
+  rc.setup(S, C.gx, C.gy, C.in, C.z0);
+
+  double sxy2[RY];
+  const double sx2 = sponge_axis_d(C.gx, S.nx, S.nb, S.inv_nb_d);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
+
+  // halo slot geometry (fixed for the whole march)
+  int hx[HS], hy[HS], hoff[HS];
+  bool hin[HS];
+#pragma unroll
+  for (int q = 0; q < HS; ++q) {
+    const int h = tid + q * NT;
+    hx[q] = 0; hy[q] = 0; hoff[q] = 0; hin[q] = false;
+    if (h < Ctx::NH) {
+      Ctx::halo_xy(h, hx[q], hy[q]);
+      const int xx = C.x0 + hx[q] - 1, yy = C.y0 + hy[q] - 1;
+      hin[q] = xx >= 0 && xx < S.nx && yy >= 0 && yy < S.ny;
+      hoff[q] = yy * S.nx + xx;
+    }
+  }
+  int coff[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
+
+  // raw inputs of one plane: own rows and halo slots
+  float2 rs[RY], rp[RY], hs_[HS], hp_[HS];
+  auto issue = [&](int zz) {
+    const bool ok = zz < S.nz;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      rs[j] = f2(0.f, 0.f); rp[j] = f2(0.f, 0.f);
+      if (ok && C.in[j]) { rs[j] = sv[zz * plane + coff[j]]; rp[j] = po[zz * plane + coff[j]]; }
+    }
+#pragma unroll
+    for (int q = 0; q < HS; ++q) {
+      hs_[q] = f2(0.f, 0.f); hp_[q] = f2(0.f, 0.f);
+      if (ok && hin[q]) { hs_[q] = sv[zz * plane + hoff[q]]; hp_[q] = po[zz * plane + hoff[q]]; }
+    }
+  };
+  // p_k = s + beta p_{k-1} of the issued plane into LDS buffer b and registers
+  float2 pnew[RY], pold[RY];
+  auto commit = [&](int b) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      pold[j] = rp[j];
+      pnew[j] = axpy2(rs[j], bf, rp[j]);
+      pl[b][1 + w * RY + j][1 + lane] = pnew[j];
+    }
+#pragma unroll
+    for (int q = 0; q < HS; ++q)
+      if (tid + q * NT < Ctx::NH) pl[b][hy[q]][hx[q]] = axpy2(hs_[q], bf, hp_[q]);
+  };
+
+  float2 pm[RY], pc[RY], pnx[RY], poc[RY], pon[RY];
+  // plane z0-1 (own rows only)
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    pm[j] = f2(0.f, 0.f);
+    if (C.in[j] && C.z0 > 0) {
+      const int c = (C.z0 - 1) * plane + coff[j];
+      pm[j] = axpy2(sv[c], bf, po[c]);
+    }
+  }
+  issue(C.z0);
+  commit(0);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) { pc[j] = pnew[j]; poc[j] = pold[j]; }
+  issue(C.z0 + 1);
+  commit(1);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) { pnx[j] = pnew[j]; pon[j] = pold[j]; }
+  issue(C.z0 + 2);
+  float2 xz[RY];
+  float mz[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    xz[j] = f2(0.f, 0.f); mz[j] = 0.f;
+    if (C.in[j]) {
+      if (aprev != 0.0) xz[j] = xv[C.z0 * plane + coff[j]];
+      mz[j] = mv[C.z0 * plane + coff[j]];
+    }
+  }
+  __syncthreads();
+
+  double acc = 0.0;
+  int cur = 0;
+  for (int z = C.z0; z < C.z1; ++z) {
+    const int b2 = (cur + 2) % 3;
+    // x and m of plane z+1 (used next step)
+    float2 xz1[RY];
+    float mz1[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      xz1[j] = f2(0.f, 0.f); mz1[j] = 0.f;
+      if (C.in[j] && z + 1 < C.z1) {
+        if (aprev != 0.0) xz1[j] = xv[(z + 1) * plane + coff[j]];
+        mz1[j] = mv[(z + 1) * plane + coff[j]];
+      }
+    }
+    // t = S p at plane z
+    const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      if (!C.in[j]) continue;
+      const int ly = w * RY + j;
+      const int c = z * plane + coff[j];
+      const float2 xm = pl[cur][ly + 1][lane];
+      const float2 xp = pl[cur][ly + 1][lane + 2];
+      const float2 ym = (j > 0) ? pc[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
+      const float2 yp = (j < RY - 1) ? pc[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
+      const double b = S.sp_scale_d * (sxy2[j] + sz2);
+      double2 td = helm(pc[j], xm, xp, ym, yp, pm[j], pnx[j], S.h2inv_d, w2 * (double)mz[j], -(S.omega_d * b));
+      if (j == srcj && z == sz) {
+        td.x -= S.alpha_c * pa_new.x;
+        td.y -= S.alpha_c * pa_new.y;
+      }
+      const float2 tv = round2(td);
+      S.t[c] = tv;
+      pn[c] = pc[j];
+      if (aprev != 0.0) xv[c] = axpy2(xz[j], af, poc[j]);
+      acc += norm2d(tv);
+      while (rc.nz_[j] == z) {
+        const int q = rc.take(S, j);
+        const float2 tq = f2((float)(S.lam_d * pc[j].x), (float)(S.lam_d * pc[j].y));
+        S.t2[q] = tq;
+        acc += norm2d(tq);
+      }
+    }
+    // plane z+2 (its loads were issued one step ago) into LDS; then prefetch z+3
+    commit(b2);
+    float2 pn2[RY], pon2[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) { pn2[j] = pnew[j]; pon2[j] = pold[j]; }
+    if (z + 3 <= C.z1) issue(z + 3);
+    __syncthreads();
+    cur = (cur + 1) % 3;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      pm[j] = pc[j]; pc[j] = pnx[j]; pnx[j] = pn2[j];
+      poc[j] = pon[j]; pon[j] = pon2[j];
+      xz[j] = xz1[j]; mz[j] = mz1[j];
+    }
+  }
+
+  const double tot = block_reduce<W>(acc, red);
+  if (tid == 0) part_d[S.slot_base + tile] = tot;
+  if (srcj >= 0) T->pa = pa_new;
+}
+
+template <int W, int RY>
+__global__ void __launch_bounds__(64 * W)
+k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_d,
+         double* __restrict__ part_s, int rhs0, int ntiles, int tiles_x, int tiles_y, int tz, int setup_only) {
+  using Ctx = TileCtx<W, RY>;
+  constexpr int NT = 64 * W;
+  constexpr int HS = (Ctx::NH + NT - 1) / NT;
+  __shared__ float2 pl[3][Ctx::LY][Ctx::LX];
+  __shared__ double red[W + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int rl = logical / ntiles;
+  const int tile = logical - rl * ntiles;
+  const int rhs = rhs0 + rl;
+  const SysDev& S = sysv[rhs];
+  SysState* T = stv + rhs;
+  if (T->status != kActive) return;
+  const int k = T->iterB;
+  const bool setup = k < 0;
+  if (setup_only && !setup) return;
+
+  double a = 0.0;
+  if (!setup) {
+    const double gk = T->gamma[k & 1];
+    const double g0 = T->gamma0;
+    const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
+    const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
+    if (stop) {
+      if (tile == 0 && tid == 0) {
+        T->status = (g0 == 0.0) ? kZeroRhs
+                  : (gk <= S.rtol2 * g0) ? kConverged
+                  : (gk > kDivergeRatio * gmin) ? kDiverged : kMaxIter;
+        T->iters = k;
+      }
+      return;
+    }
+    const double dk = block_sum_slots<W>(part_d + S.slot_base, ntiles, red);
+    if (!(dk > 0.0) || !(dk <= DBL_MAX) || !(gk <= DBL_MAX)) {
+      if (tile == 0 && tid == 0) {
+        T->status = kBreakdown;
+        T->iters = k;
+      }
+      return;
+    }
+    a = gk / dk;
+    if (tile == 0 && tid == 0) T->a[k & 1] = a;
+  }
+
+  Ctx C;
+  C.setup(S, tile, lane, w, tiles_x, tiles_y, tz);
+  const int plane = C.plane;
+  const double af = a;
+  const double w2 = S.omega_d * S.omega_d;
+  const float2* __restrict__ ro = S.r[setup ? 1 : (k & 1)];
+  float2* __restrict__ rn = S.r[setup ? 0 : ((k + 1) & 1)];
+  const float2* __restrict__ tv = S.t;
+  const float* __restrict__ mv = S.m;
+
+  const int sxy = S.src % plane, sz = S.src / plane;
+  const int sx = sxy % S.nx, sy = sxy / S.nx;
+  int srcj = -1;
+  if (S.mode == 1 && sx == C.gx && sz >= C.z0 && sz < C.z1) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+      if (C.gy[j] == sy) srcj = j;
+  }
+
+  RecCursor<RY> rc;
+  rc.setup(S, C.gx, C.gy, C.in, C.z0);
+
+  double sxy2[RY];
+  const double sx2 = sponge_axis_d(C.gx, S.nx, S.nb, S.inv_nb_d);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
+
+  int hx[HS], hy[HS], hoff[HS];
+  bool hin[HS];
+#pragma unroll
+  for (int q = 0; q < HS; ++q) {
+    const int h = tid + q * NT;
+    hx[q] = 0; hy[q] = 0; hoff[q] = 0; hin[q] = false;
+    if (h < Ctx::NH) {
+      Ctx::halo_xy(h, hx[q], hy[q]);
+      const int xx = C.x0 + hx[q] - 1, yy = C.y0 + hy[q] - 1;
+      hin[q] = xx >= 0 && xx < S.nx && yy >= 0 && yy < S.ny;
+      hoff[q] = yy * S.nx + xx;
+    }
+  }
+  int coff[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
+
+  float2 rr[RY], rt[RY], hr[HS], ht[HS];
+  auto issue = [&](int zz) {
+    const bool ok = zz < S.nz;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      rr[j] = f2(0.f, 0.f); rt[j] = f2(0.f, 0.f);
+      if (ok && C.in[j]) {
+        rr[j] = ro[zz * plane + coff[j]];
+        if (!setup) rt[j] = tv[zz * plane + coff[j]];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < HS; ++q) {
+      hr[q] = f2(0.f, 0.f); ht[q] = f2(0.f, 0.f);
+      if (ok && hin[q]) {
+        hr[q] = ro[zz * plane + hoff[q]];
+        if (!setup) ht[q] = tv[zz * plane + hoff[q]];
+      }
+    }
+  };
+  float2 rnew[RY];
+  auto commit = [&](int b) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      rnew[j] = setup ? rr[j] : axpy2(rr[j], -af, rt[j]);
+      pl[b][1 + w * RY + j][1 + lane] = rnew[j];
+    }
+#pragma unroll
+    for (int q = 0; q < HS; ++q)
+      if (tid + q * NT < Ctx::NH) pl[b][hy[q]][hx[q]] = setup ? hr[q] : axpy2(hr[q], -af, ht[q]);
+  };
+
+  float2 rm[RY], rc_[RY], rnx[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    rm[j] = f2(0.f, 0.f);
+    if (C.in[j] && C.z0 > 0) {
+      const int c = (C.z0 - 1) * plane + coff[j];
+      rm[j] = setup ? ro[c] : axpy2(ro[c], -af, tv[c]);
+    }
+  }
+  issue(C.z0);
+  commit(0);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) rc_[j] = rnew[j];
+  issue(C.z0 + 1);
+  commit(1);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) rnx[j] = rnew[j];
+  issue(C.z0 + 2);
+  float mz[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) mz[j] = C.in[j] ? mv[C.z0 * plane + coff[j]] : 0.f;
+  __syncthreads();
+
+  double acc = 0.0;
+  double2 sa = make_double2(0.0, 0.0);
+  int cur = 0;
+  for (int z = C.z0; z < C.z1; ++z) {
+    const int b2 = (cur + 2) % 3;
+    float mz1[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) mz1[j] = (C.in[j] && z + 1 < C.z1) ? mv[(z + 1) * plane + coff[j]] : 0.f;
+    const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      if (!C.in[j]) continue;
+      const int ly = w * RY + j;
+      const int c = z * plane + coff[j];
+      const float2 xm = pl[cur][ly + 1][lane];
+      const float2 xp = pl[cur][ly + 1][lane + 2];
+      const float2 ym = (j > 0) ? rc_[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
+      const float2 yp = (j < RY - 1) ? rc_[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
+      const double b = S.sp_scale_d * (sxy2[j] + sz2);
+      double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], S.h2inv_d, w2 * (double)mz[j], S.omega_d * b);
+      while (rc.nz_[j] == z) {
+        const int q = rc.take(S, j);
+        float2 r2 = S.r2[q];
+        if (!setup) {
+          r2 = axpy2(r2, -af, S.t2[q]);
+          S.r2[q] = r2;
+        }
+        sd.x += S.lam_d * r2.x;
+        sd.y += S.lam_d * r2.y;
+      }
+      const float2 s = round2(sd);
+      if (j == srcj && z == sz) {
+        sa = make_double2(-S.alpha_c * (double)rc_[j].x, -S.alpha_c * (double)rc_[j].y);
+        acc += sa.x * sa.x + sa.y * sa.y;
+      }
+      S.s[c] = s;
+      rn[c] = rc_[j];
+      acc += norm2d(s);
+    }
+    commit(b2);
+    float2 rn2[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) rn2[j] = rnew[j];
+    if (z + 3 <= C.z1) issue(z + 3);
+    __syncthreads();
+    cur = (cur + 1) % 3;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) { rm[j] = rc_[j]; rc_[j] = rnx[j]; rnx[j] = rn2[j]; mz[j] = mz1[j]; }
+  }
+
+  const double tot = block_reduce<W>(acc, red);
+  if (tid == 0) part_s[S.slot_base + tile] = tot;
+  if (tile == 0 && tid == 0) T->iterA = k + 1;
+  if (srcj >= 0) T->sa = sa;
+}
+
+// ---------------------------------------------------------------------------
 // dispatch over the supported tile shapes
 // ---------------------------------------------------------------------------
 
 #define WRI_TILE_LIST(X) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(2, 8)
 
 bool cfg_supported(const TileCfg& c) {
-#define X(W_, R_) if (c.w == W_ && c.ry == R_) return c.tz >= 1;
+#define X(W_, R_) if (c.w == W_ && c.ry == R_) return c.tz >= 1 && (c.pf == 0 || c.pf == 1);
   WRI_TILE_LIST(X)
 #undef X
   return false;
@@ -612,8 +1052,12 @@ hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const d
   if (nb == 0) return hipSuccess;
 #define X(W_, R_)                                                                              \
   if (c.w == W_ && c.ry == R_) {                                                               \
-    hipLaunchKernelGGL((k_fwd<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d, \
-                       rhs0, ntiles, tiles_x, tiles_y, c.tz);                                                          \
+    if (c.pf)                                                                                      \
+      hipLaunchKernelGGL((k_fwd_pf<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d, \
+                         rhs0, ntiles, tiles_x, tiles_y, c.tz);                                    \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_fwd<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d,    \
+                         rhs0, ntiles, tiles_x, tiles_y, c.tz);                                    \
     return hipGetLastError();                                                                  \
   }
   WRI_TILE_LIST(X)
@@ -629,8 +1073,12 @@ hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const d
   if (nb == 0) return hipSuccess;
 #define X(W_, R_)                                                                              \
   if (c.w == W_ && c.ry == R_) {                                                               \
-    hipLaunchKernelGGL((k_adj<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s, \
-                       rhs0, ntiles, tiles_x, tiles_y, c.tz, setup_only);                                                          \
+    if (c.pf)                                                                                      \
+      hipLaunchKernelGGL((k_adj_pf<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s, \
+                         rhs0, ntiles, tiles_x, tiles_y, c.tz, setup_only);                        \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_adj<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s,    \
+                         rhs0, ntiles, tiles_x, tiles_y, c.tz, setup_only);                        \
     return hipGetLastError();                                                                  \
   }
   WRI_TILE_LIST(X)

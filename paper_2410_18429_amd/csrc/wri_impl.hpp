@@ -71,9 +71,10 @@ struct SysState {
 };
 
 struct TileCfg {
-  int w;   // wavefronts per workgroup
-  int ry;  // rows per wavefront  (tile height TY = w*ry)
-  int tz;  // z-slab length
+  int w;       // wavefronts per workgroup
+  int ry;      // rows per wavefront  (tile height TY = w*ry)
+  int tz;      // z-slab length
+  int pf = 0;  // 1: software-pipelined z march (loads of plane z+2 in flight during plane z)
   int ty() const { return w * ry; }
 };
 
