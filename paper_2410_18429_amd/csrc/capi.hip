@@ -145,6 +145,7 @@ struct Layout {
   std::vector<int> set_of;          // original system -> receiver-set id
   std::vector<RecSet> sets;
   size_t off_sysdev = 0, off_state = 0, off_part_d = 0, off_part_s = 0, off_part_j = 0, off_dot = 0;
+  size_t off_gdesc = 0;
   std::vector<size_t> off_vec;      // per processing slot: base of its 7 vectors (batched) ; plain: one slot
   std::vector<size_t> off_rvec;     // per processing slot: r2, t2
   std::vector<int> slot_base;       // per processing slot
@@ -206,6 +207,7 @@ Layout make_layout(const wri_grid* grids, int n_grids, const wri_system* sys, in
   }
   L.dot_nparts = dot_parts((int)nmax);
   L.off_dot = take(sizeof(double) * (size_t)(L.dot_nparts * 2 + 16));
+  L.off_gdesc = take(sizeof(GroupDesc) * (size_t)std::max(n_grids, 1));
   for (auto& rs : L.sets) {
     const wri_grid& g = grids[rs.grid];
     rs.off_rec = take(sizeof(int32_t) * rs.rec.size());
@@ -262,7 +264,7 @@ void build_colmap(const wri_grid& g, const std::vector<int32_t>& rec, std::vecto
 // ---------------------------------------------------------------------------
 
 std::mutex g_mutex;
-std::map<std::tuple<int, int, int, int, int, int>, TileCfg> g_tuned;  // (dev, nx, ny, nz, nrhs, mode)
+std::map<std::string, TileCfg> g_tuned;  // batch signature -> tile shape
 
 struct GraphEntry {
   hipGraph_t graph = nullptr;
@@ -297,7 +299,10 @@ struct Ctx {
   Layout L;
   std::vector<SysDev> hsys;          // processing order
   std::vector<Group> groups;
-  std::vector<Tiling> tiling;        // per group
+  std::vector<Tiling> tiling;        // per group (one tile shape for all groups)
+  std::vector<GroupDesc> hgd;        // host copy of the device group table
+  int nblocks = 0;                   // blocks of one fused launch over all groups
+  GroupDesc* dgd = nullptr;
   SysDev* dsys = nullptr;
   SysState* dstate = nullptr;
   double* part_d = nullptr;
@@ -392,50 +397,63 @@ struct EventPool {
   }
 };
 
+// One tile shape for every group: per-group tile counts and the device table
+// that maps a block of a fused launch to (group, system, tile).
+int set_config(Ctx& C, const TileCfg& cfg) {
+  C.tiling.resize(C.groups.size());
+  C.hgd.resize(C.groups.size());
+  int b0 = 0;
+  for (size_t gi = 0; gi < C.groups.size(); ++gi) {
+    const Tiling t = make_tiling(cfg, C.grids[C.groups[gi].grid]);
+    C.tiling[gi] = t;
+    GroupDesc& d = C.hgd[gi];
+    d.rhs0 = C.groups[gi].rhs0;
+    d.nrhs = C.groups[gi].nrhs;
+    d.tiles_x = t.tx;
+    d.tiles_y = t.ty;
+    d.tz = cfg.tz;
+    d.ntiles = t.ntiles();
+    d.block0 = b0;
+    d.pad_ = 0;
+    b0 += d.nrhs * d.ntiles;
+  }
+  C.nblocks = b0;
+  if (!C.hgd.empty()) {
+    WRI_HIP(hipMemcpyAsync(C.dgd, C.hgd.data(), sizeof(GroupDesc) * C.hgd.size(), hipMemcpyHostToDevice, C.st));
+    WRI_HIP(hipStreamSynchronize(C.st));  // C.hgd may change before an asynchronous copy would finish
+  }
+  return WRI_OK;
+}
+
+const TileCfg& cur_cfg(const Ctx& C) { return C.tiling.front().cfg; }
+
 // eager iteration with an event pair around the forward and adjoint launches
 int launch_iteration_timed(Ctx& C, EventPool& pool, std::vector<std::pair<hipEvent_t, hipEvent_t>>& fwd,
                            std::vector<std::pair<hipEvent_t, hipEvent_t>>& adj) {
   for (int phase = 0; phase < 2; ++phase) {
-    for (size_t gi = 0; gi < C.groups.size(); ++gi) {
-      const Tiling& t = C.tiling[gi];
-      hipEvent_t a = pool.next(), b = pool.next();
-      if (!a || !b) return fail(WRI_EHIP, "hipEventCreate failed");
-      WRI_HIP(hipEventRecord(a, C.st));
-      if (phase == 0)
-        WRI_HIP(launch_fwd(t.cfg, C.dsys, C.dstate, C.part_s, C.part_d, C.groups[gi].rhs0, C.groups[gi].nrhs,
-                           t.tx, t.ty, t.tz, C.st));
-      else
-        WRI_HIP(launch_adj(t.cfg, C.dsys, C.dstate, C.part_d, C.part_s, C.groups[gi].rhs0, C.groups[gi].nrhs,
-                           t.tx, t.ty, t.tz, C.st));
-      WRI_HIP(hipEventRecord(b, C.st));
-      (phase == 0 ? fwd : adj).emplace_back(a, b);
-    }
+    hipEvent_t a = pool.next(), b = pool.next();
+    if (!a || !b) return fail(WRI_EHIP, "hipEventCreate failed");
+    WRI_HIP(hipEventRecord(a, C.st));
+    if (phase == 0)
+      WRI_HIP(launch_fwd(cur_cfg(C), C.dsys, C.dstate, C.part_s, C.part_d, C.dgd, (int)C.hgd.size(), C.nblocks, C.st));
+    else
+      WRI_HIP(launch_adj(cur_cfg(C), C.dsys, C.dstate, C.part_d, C.part_s, C.dgd, (int)C.hgd.size(), C.nblocks, C.st));
+    WRI_HIP(hipEventRecord(b, C.st));
+    (phase == 0 ? fwd : adj).emplace_back(a, b);
   }
   return WRI_OK;
 }
 
+// one CGLS iteration: the forward launch then the adjoint launch, each over all groups
 int launch_iteration(Ctx& C, hipStream_t s) {
-  for (size_t gi = 0; gi < C.groups.size(); ++gi) {
-    const Tiling& t = C.tiling[gi];
-    WRI_HIP(launch_fwd(t.cfg, C.dsys, C.dstate, C.part_s, C.part_d, C.groups[gi].rhs0, C.groups[gi].nrhs,
-                       t.tx, t.ty, t.tz, s));
-  }
-  for (size_t gi = 0; gi < C.groups.size(); ++gi) {
-    const Tiling& t = C.tiling[gi];
-    WRI_HIP(launch_adj(t.cfg, C.dsys, C.dstate, C.part_d, C.part_s, C.groups[gi].rhs0, C.groups[gi].nrhs,
-                       t.tx, t.ty, t.tz, s));
-  }
+  WRI_HIP(launch_fwd(cur_cfg(C), C.dsys, C.dstate, C.part_s, C.part_d, C.dgd, (int)C.hgd.size(), C.nblocks, s));
+  WRI_HIP(launch_adj(cur_cfg(C), C.dsys, C.dstate, C.part_d, C.part_s, C.dgd, (int)C.hgd.size(), C.nblocks, s));
   return WRI_OK;
 }
 
-int launch_setup(Ctx& C, int only_group = -1) {
+int launch_setup(Ctx& C) {
   WRI_HIP(launch_init(C.dsys, C.dstate, C.n_sys, C.st));
-  for (size_t gi = 0; gi < C.groups.size(); ++gi) {
-    if (only_group >= 0 && (int)gi != only_group) continue;
-    const Tiling& t = C.tiling[gi];
-    WRI_HIP(launch_adj(t.cfg, C.dsys, C.dstate, C.part_d, C.part_s, C.groups[gi].rhs0, C.groups[gi].nrhs,
-                       t.tx, t.ty, t.tz, C.st));
-  }
+  WRI_HIP(launch_adj(cur_cfg(C), C.dsys, C.dstate, C.part_d, C.part_s, C.dgd, (int)C.hgd.size(), C.nblocks, C.st));
   return WRI_OK;
 }
 
@@ -458,60 +476,54 @@ bool forced_tile(TileCfg* out) {
   return false;
 }
 
-// time a few iterations of one group per candidate tile; keep the fastest
+// Time a few real iterations of the whole batch per candidate tile shape and
+// keep the fastest; cached per (device, mode, grid shapes and system counts).
 int autotune(Ctx& C) {
-  TileCfg forced;
-  if (forced_tile(&forced)) {
-    for (size_t gi = 0; gi < C.groups.size(); ++gi) C.tiling[gi] = make_tiling(forced, C.grids[C.groups[gi].grid]);
-    return WRI_OK;
+  std::string key;
+  int64_t total = 0;
+  {
+    char buf[96];
+    snprintf(buf, sizeof(buf), "%d|%d|", C.dev, C.mode);
+    key = buf;
+    for (const auto& G : C.groups) {
+      const wri_grid& g = C.grids[G.grid];
+      snprintf(buf, sizeof(buf), "%dx%dx%d:%d;", g.nx, g.ny, g.nz, G.nrhs);
+      key += buf;
+      total += cells(g) * G.nrhs;
+    }
   }
-  for (size_t gi = 0; gi < C.groups.size(); ++gi) {
-    const Group& G = C.groups[gi];
-    const wri_grid& g = C.grids[G.grid];
-    const auto key = std::make_tuple(C.dev, g.nx, g.ny, g.nz, G.nrhs, C.mode);
-    auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
-      C.tiling[gi] = make_tiling(it->second, g);
-      continue;
-    }
-    if (cells(g) < 64 * 64 * 16) {  // too small for the choice to matter
-      g_tuned[key] = kCands[0];
-      continue;
-    }
-    hipEvent_t e0, e1;
-    WRI_HIP(hipEventCreate(&e0));
-    WRI_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
-    TileCfg best_cfg = kCands[0];
-    for (int c = 0; c < kNumCands; ++c) {
-      C.tiling[gi] = make_tiling(kCands[c], g);
-      int rc = launch_setup(C, (int)gi);
-      if (rc != WRI_OK) return rc;
-      std::vector<Group> saved = C.groups;
-      std::vector<Tiling> saved_t = C.tiling;
-      C.groups = {G};
-      C.tiling = {saved_t[gi]};
-      rc = launch_iteration(C, C.st);  // warm
-      if (rc == WRI_OK) WRI_HIP(hipEventRecord(e0, C.st));
-      for (int it2 = 0; it2 < 3 && rc == WRI_OK; ++it2) rc = launch_iteration(C, C.st);
-      C.groups = saved;
-      C.tiling = saved_t;
-      if (rc != WRI_OK) return rc;
-      WRI_HIP(hipEventRecord(e1, C.st));
-      WRI_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      WRI_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (verbose())
-        fprintf(stderr, "[wri] autotune grid %dx%dx%d nrhs %d: w=%d ry=%d tz=%d pf=%d -> %.3f ms / 3 iterations\n",
-                g.nx, g.ny, g.nz, G.nrhs, kCands[c].w, kCands[c].ry, kCands[c].tz, kCands[c].pf, ms);
-      if (ms < best) { best = ms; best_cfg = kCands[c]; }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    g_tuned[key] = best_cfg;
-    C.tiling[gi] = make_tiling(best_cfg, g);
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) return set_config(C, it->second);
+  if (total < (int64_t)64 * 64 * 64) {  // too small for the choice to matter
+    g_tuned[key] = kCands[0];
+    return set_config(C, kCands[0]);
   }
-  return WRI_OK;
+  hipEvent_t e0, e1;
+  WRI_HIP(hipEventCreate(&e0));
+  WRI_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  TileCfg best_cfg = kCands[0];
+  for (int c = 0; c < kNumCands; ++c) {
+    int rc = set_config(C, kCands[c]);
+    if (rc == WRI_OK) rc = launch_setup(C);
+    if (rc == WRI_OK) rc = launch_iteration(C, C.st);  // warm
+    if (rc != WRI_OK) return rc;
+    WRI_HIP(hipEventRecord(e0, C.st));
+    for (int it2 = 0; it2 < 3 && rc == WRI_OK; ++it2) rc = launch_iteration(C, C.st);
+    if (rc != WRI_OK) return rc;
+    WRI_HIP(hipEventRecord(e1, C.st));
+    WRI_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    WRI_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (verbose())
+      fprintf(stderr, "[wri] autotune %s w=%d ry=%d tz=%d pf=%d -> %.3f ms / 3 iterations\n", key.c_str(),
+              kCands[c].w, kCands[c].ry, kCands[c].tz, kCands[c].pf, ms);
+    if (ms < best) { best = ms; best_cfg = kCands[c]; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_tuned[key] = best_cfg;
+  return set_config(C, best_cfg);
 }
 
 std::string graph_key(const Ctx& C, int chunk) {
@@ -519,10 +531,11 @@ std::string graph_key(const Ctx& C, int chunk) {
   char buf[128];
   snprintf(buf, sizeof(buf), "%d|%p|%d|", C.dev, (void*)C.ws, chunk);
   k += buf;
-  for (size_t gi = 0; gi < C.groups.size(); ++gi) {
-    const Tiling& t = C.tiling[gi];
-    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d,%d,%d,%d;", C.groups[gi].rhs0, C.groups[gi].nrhs, t.cfg.w,
-             t.cfg.ry, t.cfg.tz, t.cfg.pf, t.tx, t.ty, t.tz);
+  const TileCfg& c = cur_cfg(C);
+  snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d;", c.w, c.ry, c.tz, c.pf, C.nblocks);
+  k += buf;
+  for (const auto& d : C.hgd) {
+    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d;", d.rhs0, d.nrhs, d.tiles_x, d.tiles_y, d.tz, d.block0);
     k += buf;
   }
   return k;
@@ -580,20 +593,16 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     if (C.groups.empty() || C.groups.back().grid != g) C.groups.push_back({g, p, 0});
     C.groups.back().nrhs++;
   }
-  C.tiling.resize(C.groups.size());
-  for (size_t gi = 0; gi < C.groups.size(); ++gi) C.tiling[gi] = make_tiling(kCands[0], C.grids[C.groups[gi].grid]);
 
   if (C.n_sys > 0) {
     WRI_HIP(hipMemcpyAsync(C.dsys, C.hsys.data(), sizeof(SysDev) * C.n_sys, hipMemcpyHostToDevice, C.st));
     int rc = upload_receivers(C);
     if (rc != WRI_OK) return rc;
     TileCfg forced;
-    if (forced_tile(&forced)) {
-      for (size_t gi = 0; gi < C.groups.size(); ++gi) C.tiling[gi] = make_tiling(forced, C.grids[C.groups[gi].grid]);
-    } else if (!(C.flags & WRI_FLAG_NO_AUTOTUNE)) {
-      rc = autotune(C);
-      if (rc != WRI_OK) return rc;
-    }
+    if (forced_tile(&forced)) rc = set_config(C, forced);
+    else if (!(C.flags & WRI_FLAG_NO_AUTOTUNE)) rc = autotune(C);
+    else rc = set_config(C, kCands[0]);
+    if (rc != WRI_OK) return rc;
     if (verbose())
       for (size_t gi = 0; gi < C.groups.size(); ++gi)
         fprintf(stderr, "[wri] grid %d (%d systems): tile w=%d ry=%d tz=%d pf=%d, %d tiles per system\n",
@@ -816,6 +825,7 @@ int solve_common(const wri_grid* grids, int32_t n_grids, const float* const* m, 
   C.part_s = at<double>(C.ws, C.L.off_part_s);
   C.part_j = at<double>(C.ws, C.L.off_part_j);
   C.dot = at<double>(C.ws, C.L.off_dot);
+  C.dgd = at<GroupDesc>(C.ws, C.L.off_gdesc);
   std::lock_guard<std::mutex> lock(g_mutex);
   WRI_HIP(hipGetDevice(&C.dev));
   std::vector<SysState> hs;

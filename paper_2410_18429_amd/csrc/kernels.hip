@@ -244,16 +244,20 @@ struct RecCursor {
 template <int W, int RY>
 __global__ void __launch_bounds__(64 * W)
 k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_s,
-      double* __restrict__ part_d, int rhs0, int ntiles, int tiles_x, int tiles_y, int tz) {
+      double* __restrict__ part_d, const GroupDesc* __restrict__ gd, int ngroups) {
   using Ctx = TileCtx<W, RY>;
   __shared__ float2 pl[2][Ctx::LY][Ctx::LX];
   __shared__ double red[W + 1];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int rl = logical / ntiles;
-  const int tile = logical - rl * ntiles;
-  const int rhs = rhs0 + rl;
+  int g = 0;
+  while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
+  const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
+  const int local = logical - gd[g].block0;
+  const int rl = local / ntiles;
+  const int tile = local - rl * ntiles;
+  const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
   if (T->status != kActive) return;
@@ -431,16 +435,20 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
 template <int W, int RY>
 __global__ void __launch_bounds__(64 * W)
 k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_d,
-      double* __restrict__ part_s, int rhs0, int ntiles, int tiles_x, int tiles_y, int tz, int setup_only) {
+      double* __restrict__ part_s, const GroupDesc* __restrict__ gd, int ngroups, int setup_only) {
   using Ctx = TileCtx<W, RY>;
   __shared__ float2 pl[2][Ctx::LY][Ctx::LX];
   __shared__ double red[W + 1];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int rl = logical / ntiles;
-  const int tile = logical - rl * ntiles;
-  const int rhs = rhs0 + rl;
+  int g = 0;
+  while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
+  const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
+  const int local = logical - gd[g].block0;
+  const int rl = local / ntiles;
+  const int tile = local - rl * ntiles;
+  const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
   if (T->status != kActive) return;
@@ -601,7 +609,7 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
 template <int W, int RY>
 __global__ void __launch_bounds__(64 * W)
 k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_s,
-         double* __restrict__ part_d, int rhs0, int ntiles, int tiles_x, int tiles_y, int tz) {
+         double* __restrict__ part_d, const GroupDesc* __restrict__ gd, int ngroups) {
   using Ctx = TileCtx<W, RY>;
   constexpr int NT = 64 * W;
   constexpr int HS = (Ctx::NH + NT - 1) / NT;  // halo slots per thread
@@ -610,9 +618,13 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int rl = logical / ntiles;
-  const int tile = logical - rl * ntiles;
-  const int rhs = rhs0 + rl;
+  int g = 0;
+  while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
+  const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
+  const int local = logical - gd[g].block0;
+  const int rl = local / ntiles;
+  const int tile = local - rl * ntiles;
+  const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
   if (T->status != kActive) return;
@@ -830,7 +842,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 template <int W, int RY>
 __global__ void __launch_bounds__(64 * W)
 k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_d,
-         double* __restrict__ part_s, int rhs0, int ntiles, int tiles_x, int tiles_y, int tz, int setup_only) {
+         double* __restrict__ part_s, const GroupDesc* __restrict__ gd, int ngroups, int setup_only) {
   using Ctx = TileCtx<W, RY>;
   constexpr int NT = 64 * W;
   constexpr int HS = (Ctx::NH + NT - 1) / NT;
@@ -839,9 +851,13 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int rl = logical / ntiles;
-  const int tile = logical - rl * ntiles;
-  const int rhs = rhs0 + rl;
+  int g = 0;
+  while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
+  const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
+  const int local = logical - gd[g].block0;
+  const int rl = local / ntiles;
+  const int tile = local - rl * ntiles;
+  const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
   if (T->status != kActive) return;
@@ -1044,42 +1060,38 @@ bool cfg_supported(const TileCfg& c) {
   return false;
 }
 
-hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_s,
-                      double* part_d, int rhs0, int nrhs, int tiles_x, int tiles_y, int tiles_z,
-                      hipStream_t s) {
-  const int ntiles = tiles_x * tiles_y * tiles_z;
-  const unsigned nb = (unsigned)nrhs * (unsigned)ntiles;
-  if (nb == 0) return hipSuccess;
-#define X(W_, R_)                                                                              \
-  if (c.w == W_ && c.ry == R_) {                                                               \
-    if (c.pf)                                                                                      \
-      hipLaunchKernelGGL((k_fwd_pf<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d, \
-                         rhs0, ntiles, tiles_x, tiles_y, c.tz);                                    \
-    else                                                                                           \
-      hipLaunchKernelGGL((k_fwd<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d,    \
-                         rhs0, ntiles, tiles_x, tiles_y, c.tz);                                    \
-    return hipGetLastError();                                                                  \
+hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_s, double* part_d,
+                      const GroupDesc* gd, int ngroups, int nblocks, hipStream_t s) {
+  if (nblocks <= 0 || ngroups <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)nblocks;
+#define X(W_, R_)                                                                                   \
+  if (c.w == W_ && c.ry == R_) {                                                                    \
+    if (c.pf)                                                                                       \
+      hipLaunchKernelGGL((k_fwd_pf<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d,  \
+                         gd, ngroups);                                                              \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_fwd<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d,     \
+                         gd, ngroups);                                                              \
+    return hipGetLastError();                                                                       \
   }
   WRI_TILE_LIST(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_d,
-                      double* part_s, int rhs0, int nrhs, int tiles_x, int tiles_y, int tiles_z,
-                      hipStream_t s, int setup_only) {
-  const int ntiles = tiles_x * tiles_y * tiles_z;
-  const unsigned nb = (unsigned)nrhs * (unsigned)ntiles;
-  if (nb == 0) return hipSuccess;
-#define X(W_, R_)                                                                              \
-  if (c.w == W_ && c.ry == R_) {                                                               \
-    if (c.pf)                                                                                      \
-      hipLaunchKernelGGL((k_adj_pf<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s, \
-                         rhs0, ntiles, tiles_x, tiles_y, c.tz, setup_only);                        \
-    else                                                                                           \
-      hipLaunchKernelGGL((k_adj<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s,    \
-                         rhs0, ntiles, tiles_x, tiles_y, c.tz, setup_only);                        \
-    return hipGetLastError();                                                                  \
+hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_d, double* part_s,
+                      const GroupDesc* gd, int ngroups, int nblocks, hipStream_t s, int setup_only) {
+  if (nblocks <= 0 || ngroups <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)nblocks;
+#define X(W_, R_)                                                                                   \
+  if (c.w == W_ && c.ry == R_) {                                                                    \
+    if (c.pf)                                                                                       \
+      hipLaunchKernelGGL((k_adj_pf<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s,  \
+                         gd, ngroups, setup_only);                                                  \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_adj<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s,     \
+                         gd, ngroups, setup_only);                                                  \
+    return hipGetLastError();                                                                       \
   }
   WRI_TILE_LIST(X)
 #undef X

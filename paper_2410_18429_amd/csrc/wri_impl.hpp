@@ -78,16 +78,24 @@ struct TileCfg {
   int ty() const { return w * ry; }
 };
 
+// One group = the systems of one grid.  A fused launch covers every group:
+// blocks [block0, block0 + nrhs*ntiles) belong to the group, ntiles =
+// tiles_x*tiles_y*tiles_z slab tiles per system.
+struct GroupDesc {
+  int rhs0, nrhs;
+  int tiles_x, tiles_y, tz;
+  int ntiles;
+  int block0;
+  int pad_;
+};
+
 // ---- launchers (kernels.hip) -------------------------------------------
 hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s);
-// Fused CGLS launches over systems rhs0 .. rhs0+nrhs-1 (all on one grid),
-// tiles_x*tiles_y*tiles_z slab tiles of shape (64, c.ty(), c.tz) per system.
-hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_s,
-                      double* part_d, int rhs0, int nrhs, int tiles_x, int tiles_y, int tiles_z,
-                      hipStream_t s);
-hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_d,
-                      double* part_s, int rhs0, int nrhs, int tiles_x, int tiles_y, int tiles_z,
-                      hipStream_t s, int setup_only = 0);
+// Fused CGLS launches over all groups (same tile shape c for all of them).
+hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_s, double* part_d,
+                      const GroupDesc* gd, int ngroups, int nblocks, hipStream_t s);
+hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_d, double* part_s,
+                      const GroupDesc* gd, int ngroups, int nblocks, hipStream_t s, int setup_only = 0);
 hipError_t launch_grad(const SysDev* sys, SysState* st, int rhs0, int nrhs, int n, float* grad,
                        double* part_j, int stride, int accumulate, hipStream_t s);
 hipError_t launch_finalize(const SysDev* sys, SysState* st, const double* part_j, int nparts,
