@@ -35,6 +35,27 @@ namespace wri {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// Vector pointers read from the device-resident system table are generic
+// (flat) to the compiler; flat accesses also count against the LDS wait
+// counter, which ties every LDS wait to the outstanding HBM loads.  All solver
+// vectors live in global memory, so the fused kernels access them through
+// address-space-1 pointers (global_load / global_store).
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL T* gptr(T* p) { return (GLOBAL T*)p; }
+template <class T>
+__device__ __forceinline__ const GLOBAL T* gptr(const T* p) { return (const GLOBAL T*)p; }
+// 8-byte element access through a global pointer (one dwordx2 load/store)
+__device__ __forceinline__ float2 ld2(const GLOBAL float2* p, int i) {
+  return __builtin_bit_cast(float2, *((const GLOBAL unsigned long long*)p + i));
+}
+__device__ __forceinline__ void st2(GLOBAL float2* p, int i, float2 v) {
+  *((GLOBAL unsigned long long*)p + i) = __builtin_bit_cast(unsigned long long, v);
+}
+__device__ __forceinline__ int2 ld2i(const GLOBAL int2* p, int i) {
+  return __builtin_bit_cast(int2, *((const GLOBAL unsigned long long*)p + i));
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   // Blocks go round-robin to the XCDs; give each XCD a contiguous range of
   // logical tiles so that halo re-reads of neighbouring tiles hit its L2.
@@ -221,18 +242,18 @@ struct RecCursor {
     for (int j = 0; j < RY; ++j) {
       cur[j] = 0; end[j] = 0; nz_[j] = INT_MAX;
       if (S.colmap != nullptr && in[j]) {
-        const int2 be = S.colmap[gy[j] * S.nx + gx];
+        const int2 be = ld2i(gptr(S.colmap), gy[j] * S.nx + gx);
         int c = be.x;
-        while (c < be.y && S.entries[c].x < z0) ++c;
+        while (c < be.y && ld2i(gptr(S.entries), c).x < z0) ++c;
         cur[j] = c; end[j] = be.y;
-        nz_[j] = (c < be.y) ? S.entries[c].x : INT_MAX;
+        nz_[j] = (c < be.y) ? ld2i(gptr(S.entries), c).x : INT_MAX;
       }
     }
   }
   __device__ int take(const SysDev& S, int j) {  // receiver index at the current z; advance
-    const int q = S.entries[cur[j]].y;
+    const int q = ld2i(gptr(S.entries), cur[j]).y;
     ++cur[j];
-    nz_[j] = (cur[j] < end[j]) ? S.entries[cur[j]].x : INT_MAX;
+    nz_[j] = (cur[j] < end[j]) ? ld2i(gptr(S.entries), cur[j]).x : INT_MAX;
     return q;
   }
 };
@@ -282,10 +303,13 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   const double af = aprev;
   const double bf = beta;
   const double w2 = S.omega_d * S.omega_d;
-  const float2* __restrict__ sv = S.s;
-  const float2* __restrict__ po = S.p[k & 1];
-  float2* __restrict__ pn = S.p[(k + 1) & 1];
-  float2* __restrict__ xv = S.x;
+  const GLOBAL float2* __restrict__ sv = gptr((const float2*)S.s);
+  const GLOBAL float2* __restrict__ po = gptr((const float2*)S.p[k & 1]);
+  GLOBAL float2* __restrict__ pn = gptr(S.p[(k + 1) & 1]);
+  GLOBAL float2* __restrict__ xv = gptr(S.x);
+  const GLOBAL float* __restrict__ mv = gptr(S.m);
+  GLOBAL float2* __restrict__ tout = gptr(S.t);
+  GLOBAL float2* __restrict__ t2v = gptr(S.t2);
 
   // source cell: which of my rows (if any) holds it
   const int sxy = S.src % plane, sz = S.src / plane;
@@ -305,7 +329,7 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
         for (int j = 0; j < RY; ++j) {
           if (!C.in[j]) continue;
           const int c = z * plane + C.gy[j] * S.nx + C.gx;
-          xv[c] = axpy2(xv[c], af, po[c]);
+          st2(xv, c, axpy2(ld2(xv, c), af, ld2(po, c)));
         }
       }
       if (srcj >= 0) {
@@ -332,7 +356,7 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
 #pragma unroll
   for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
 
-  auto pval = [&](int c) -> float2 { return axpy2(sv[c], bf, po[c]); };
+  auto pval = [&](int c) -> float2 { return axpy2(ld2(sv, c), bf, ld2(po, c)); };
 
   float2 pm[RY], pc[RY], pnx[RY], poc[RY], pon[RY];
   // plane z0 - 1 and z0
@@ -344,8 +368,8 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
     if (C.in[j]) {
       const int c = C.z0 * plane + C.gy[j] * S.nx + C.gx;
       if (C.z0 > 0) pm[j] = pval(c - plane);
-      poc[j] = po[c];
-      pc[j] = axpy2(sv[c], bf, poc[j]);
+      poc[j] = ld2(po, c);
+      pc[j] = axpy2(ld2(sv, c), bf, poc[j]);
     }
     pl[0][1 + w * RY + j][1 + lane] = pc[j];
   }
@@ -371,8 +395,8 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
       pon[j] = f2(0.f, 0.f);
       if (C.in[j] && has_next) {
         const int c = (z + 1) * plane + C.gy[j] * S.nx + C.gx;
-        pon[j] = po[c];
-        pnx[j] = axpy2(sv[c], bf, pon[j]);
+        pon[j] = ld2(po, c);
+        pnx[j] = axpy2(ld2(sv, c), bf, pon[j]);
       }
     }
     for (int h = tid; h < Ctx::NH; h += 64 * W) {
@@ -399,20 +423,20 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
       const float2 ym = (j > 0) ? pc[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
       const float2 yp = (j < RY - 1) ? pc[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
       const double b = S.sp_scale_d * (sxy2[j] + sz2);
-      double2 td = helm(pc[j], xm, xp, ym, yp, pm[j], pnx[j], S.h2inv_d, w2 * (double)S.m[c], -(S.omega_d * b));
+      double2 td = helm(pc[j], xm, xp, ym, yp, pm[j], pnx[j], S.h2inv_d, w2 * (double)mv[c], -(S.omega_d * b));
       if (j == srcj && z == sz) {
         td.x -= S.alpha_c * pa_new.x;
         td.y -= S.alpha_c * pa_new.y;
       }
       const float2 tv = round2(td);
-      S.t[c] = tv;
-      pn[c] = pc[j];
-      if (aprev != 0.0) xv[c] = axpy2(xv[c], af, poc[j]);
+      st2(tout, c, tv);
+      st2(pn, c, pc[j]);
+      if (aprev != 0.0) st2(xv, c, axpy2(ld2(xv, c), af, poc[j]));
       acc += norm2d(tv);
       while (rc.nz_[j] == z) {
         const int q = rc.take(S, j);
         const float2 tq = f2((float)(S.lam_d * pc[j].x), (float)(S.lam_d * pc[j].y));
-        S.t2[q] = tq;
+        st2(t2v, q, tq);
         acc += norm2d(tq);
       }
     }
@@ -488,9 +512,13 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   const int plane = C.plane;
   const double af = a;
   const double w2 = S.omega_d * S.omega_d;
-  const float2* __restrict__ ro = S.r[setup ? 1 : (k & 1)];
-  float2* __restrict__ rn = S.r[setup ? 0 : ((k + 1) & 1)];
-  const float2* __restrict__ tv = S.t;
+  const GLOBAL float2* __restrict__ ro = gptr((const float2*)S.r[setup ? 1 : (k & 1)]);
+  GLOBAL float2* __restrict__ rn = gptr(S.r[setup ? 0 : ((k + 1) & 1)]);
+  const GLOBAL float2* __restrict__ tv = gptr((const float2*)S.t);
+  GLOBAL float2* __restrict__ sout = gptr(S.s);
+  const GLOBAL float* __restrict__ mv = gptr(S.m);
+  GLOBAL float2* __restrict__ r2v = gptr(S.r2);
+  const GLOBAL float2* __restrict__ t2v = gptr((const float2*)S.t2);
 
   const int sxy = S.src % plane, sz = S.src / plane;
   const int sx = sxy % S.nx, sy = sxy / S.nx;
@@ -509,7 +537,10 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
 #pragma unroll
   for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
 
-  auto rval = [&](int c) -> float2 { return setup ? ro[c] : axpy2(ro[c], -af, tv[c]); };
+  auto rval = [&](int c) -> float2 {
+    const float2 r = ld2(ro, c);
+    return setup ? r : axpy2(r, -af, ld2(tv, c));
+  };
 
   float2 rm[RY], rc_[RY], rnx[RY];
 #pragma unroll
@@ -567,13 +598,13 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
       const float2 ym = (j > 0) ? rc_[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
       const float2 yp = (j < RY - 1) ? rc_[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
       const double b = S.sp_scale_d * (sxy2[j] + sz2);
-      double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], S.h2inv_d, w2 * (double)S.m[c], S.omega_d * b);
+      double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], S.h2inv_d, w2 * (double)mv[c], S.omega_d * b);
       while (rc.nz_[j] == z) {
         const int q = rc.take(S, j);
-        float2 r2 = S.r2[q];
+        float2 r2 = ld2(r2v, q);
         if (!setup) {
-          r2 = axpy2(r2, -af, S.t2[q]);
-          S.r2[q] = r2;
+          r2 = axpy2(r2, -af, ld2(t2v, q));
+          st2(r2v, q, r2);
         }
         sd.x += S.lam_d * r2.x;
         sd.y += S.lam_d * r2.y;
@@ -583,8 +614,8 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
         sa = make_double2(-S.alpha_c * (double)rc_[j].x, -S.alpha_c * (double)rc_[j].y);
         acc += sa.x * sa.x + sa.y * sa.y;
       }
-      S.s[c] = s;
-      rn[c] = rc_[j];
+      st2(sout, c, s);
+      st2(rn, c, rc_[j]);
       acc += norm2d(s);
     }
     __syncthreads();
@@ -648,11 +679,13 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   const int plane = C.plane;
   const double af = aprev, bf = beta;
   const double w2 = S.omega_d * S.omega_d;
-  const float2* __restrict__ sv = S.s;
-  const float2* __restrict__ po = S.p[k & 1];
-  float2* __restrict__ pn = S.p[(k + 1) & 1];
-  float2* __restrict__ xv = S.x;
-  const float* __restrict__ mv = S.m;
+  const GLOBAL float2* __restrict__ sv = gptr((const float2*)S.s);
+  const GLOBAL float2* __restrict__ po = gptr((const float2*)S.p[k & 1]);
+  GLOBAL float2* __restrict__ pn = gptr(S.p[(k + 1) & 1]);
+  GLOBAL float2* __restrict__ xv = gptr(S.x);
+  GLOBAL float2* __restrict__ tout = gptr(S.t);
+  GLOBAL float2* __restrict__ t2v = gptr(S.t2);
+  const GLOBAL float* __restrict__ mv = gptr(S.m);
 
   const int sxy = S.src % plane, sz = S.src / plane;
   const int sx = sxy % S.nx, sy = sxy / S.nx;
@@ -670,7 +703,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
         for (int j = 0; j < RY; ++j) {
           if (!C.in[j]) continue;
           const int c = z * plane + C.gy[j] * S.nx + C.gx;
-          xv[c] = axpy2(xv[c], af, po[c]);
+          st2(xv, c, axpy2(ld2(xv, c), af, ld2(po, c)));
         }
       }
       if (srcj >= 0) {
@@ -721,12 +754,12 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       rs[j] = f2(0.f, 0.f); rp[j] = f2(0.f, 0.f);
-      if (ok && C.in[j]) { rs[j] = sv[zz * plane + coff[j]]; rp[j] = po[zz * plane + coff[j]]; }
+      if (ok && C.in[j]) { rs[j] = ld2(sv, zz * plane + coff[j]); rp[j] = ld2(po, zz * plane + coff[j]); }
     }
 #pragma unroll
     for (int q = 0; q < HS; ++q) {
       hs_[q] = f2(0.f, 0.f); hp_[q] = f2(0.f, 0.f);
-      if (ok && hin[q]) { hs_[q] = sv[zz * plane + hoff[q]]; hp_[q] = po[zz * plane + hoff[q]]; }
+      if (ok && hin[q]) { hs_[q] = ld2(sv, zz * plane + hoff[q]); hp_[q] = ld2(po, zz * plane + hoff[q]); }
     }
   };
   // p_k = s + beta p_{k-1} of the issued plane into LDS buffer b and registers
@@ -750,7 +783,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
     pm[j] = f2(0.f, 0.f);
     if (C.in[j] && C.z0 > 0) {
       const int c = (C.z0 - 1) * plane + coff[j];
-      pm[j] = axpy2(sv[c], bf, po[c]);
+      pm[j] = axpy2(ld2(sv, c), bf, ld2(po, c));
     }
   }
   issue(C.z0);
@@ -768,7 +801,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   for (int j = 0; j < RY; ++j) {
     xz[j] = f2(0.f, 0.f); mz[j] = 0.f;
     if (C.in[j]) {
-      if (aprev != 0.0) xz[j] = xv[C.z0 * plane + coff[j]];
+      if (aprev != 0.0) xz[j] = ld2(xv, C.z0 * plane + coff[j]);
       mz[j] = mv[C.z0 * plane + coff[j]];
     }
   }
@@ -785,7 +818,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
     for (int j = 0; j < RY; ++j) {
       xz1[j] = f2(0.f, 0.f); mz1[j] = 0.f;
       if (C.in[j] && z + 1 < C.z1) {
-        if (aprev != 0.0) xz1[j] = xv[(z + 1) * plane + coff[j]];
+        if (aprev != 0.0) xz1[j] = ld2(xv, (z + 1) * plane + coff[j]);
         mz1[j] = mv[(z + 1) * plane + coff[j]];
       }
     }
@@ -807,14 +840,14 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
         td.y -= S.alpha_c * pa_new.y;
       }
       const float2 tv = round2(td);
-      S.t[c] = tv;
-      pn[c] = pc[j];
-      if (aprev != 0.0) xv[c] = axpy2(xz[j], af, poc[j]);
+      st2(tout, c, tv);
+      st2(pn, c, pc[j]);
+      if (aprev != 0.0) st2(xv, c, axpy2(xz[j], af, poc[j]));
       acc += norm2d(tv);
       while (rc.nz_[j] == z) {
         const int q = rc.take(S, j);
         const float2 tq = f2((float)(S.lam_d * pc[j].x), (float)(S.lam_d * pc[j].y));
-        S.t2[q] = tq;
+        st2(t2v, q, tq);
         acc += norm2d(tq);
       }
     }
@@ -897,10 +930,13 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   const int plane = C.plane;
   const double af = a;
   const double w2 = S.omega_d * S.omega_d;
-  const float2* __restrict__ ro = S.r[setup ? 1 : (k & 1)];
-  float2* __restrict__ rn = S.r[setup ? 0 : ((k + 1) & 1)];
-  const float2* __restrict__ tv = S.t;
-  const float* __restrict__ mv = S.m;
+  const GLOBAL float2* __restrict__ ro = gptr((const float2*)S.r[setup ? 1 : (k & 1)]);
+  GLOBAL float2* __restrict__ rn = gptr(S.r[setup ? 0 : ((k + 1) & 1)]);
+  const GLOBAL float2* __restrict__ tv = gptr((const float2*)S.t);
+  GLOBAL float2* __restrict__ sout = gptr(S.s);
+  GLOBAL float2* __restrict__ r2v = gptr(S.r2);
+  const GLOBAL float2* __restrict__ t2v = gptr((const float2*)S.t2);
+  const GLOBAL float* __restrict__ mv = gptr(S.m);
 
   const int sxy = S.src % plane, sz = S.src / plane;
   const int sx = sxy % S.nx, sy = sxy / S.nx;
@@ -943,16 +979,16 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
     for (int j = 0; j < RY; ++j) {
       rr[j] = f2(0.f, 0.f); rt[j] = f2(0.f, 0.f);
       if (ok && C.in[j]) {
-        rr[j] = ro[zz * plane + coff[j]];
-        if (!setup) rt[j] = tv[zz * plane + coff[j]];
+        rr[j] = ld2(ro, zz * plane + coff[j]);
+        if (!setup) rt[j] = ld2(tv, zz * plane + coff[j]);
       }
     }
 #pragma unroll
     for (int q = 0; q < HS; ++q) {
       hr[q] = f2(0.f, 0.f); ht[q] = f2(0.f, 0.f);
       if (ok && hin[q]) {
-        hr[q] = ro[zz * plane + hoff[q]];
-        if (!setup) ht[q] = tv[zz * plane + hoff[q]];
+        hr[q] = ld2(ro, zz * plane + hoff[q]);
+        if (!setup) ht[q] = ld2(tv, zz * plane + hoff[q]);
       }
     }
   };
@@ -974,7 +1010,8 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
     rm[j] = f2(0.f, 0.f);
     if (C.in[j] && C.z0 > 0) {
       const int c = (C.z0 - 1) * plane + coff[j];
-      rm[j] = setup ? ro[c] : axpy2(ro[c], -af, tv[c]);
+      const float2 r0 = ld2(ro, c);
+      rm[j] = setup ? r0 : axpy2(r0, -af, ld2(tv, c));
     }
   }
   issue(C.z0);
@@ -1013,10 +1050,10 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], S.h2inv_d, w2 * (double)mz[j], S.omega_d * b);
       while (rc.nz_[j] == z) {
         const int q = rc.take(S, j);
-        float2 r2 = S.r2[q];
+        float2 r2 = ld2(r2v, q);
         if (!setup) {
-          r2 = axpy2(r2, -af, S.t2[q]);
-          S.r2[q] = r2;
+          r2 = axpy2(r2, -af, ld2(t2v, q));
+          st2(r2v, q, r2);
         }
         sd.x += S.lam_d * r2.x;
         sd.y += S.lam_d * r2.y;
@@ -1026,8 +1063,8 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
         sa = make_double2(-S.alpha_c * (double)rc_[j].x, -S.alpha_c * (double)rc_[j].y);
         acc += sa.x * sa.x + sa.y * sa.y;
       }
-      S.s[c] = s;
-      rn[c] = rc_[j];
+      st2(sout, c, s);
+      st2(rn, c, rc_[j]);
       acc += norm2d(s);
     }
     commit(b2);
