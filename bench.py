@@ -75,6 +75,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--plain-sample", type=int, default=3)
+    ap.add_argument("--probe-iters", type=int, default=0,
+                    help="counter runs: only run the batch for this many CGLS iterations and exit")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="counter calibration: copy a buffer of this many MiB three times and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -86,6 +90,15 @@ def main():
     from paper_2410_18429_amd import wri
 
     dev = "cuda:0"
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return
     prob = wri_synth.make_config(args.config, seed=0)
     g = prob.grids[0]
     nsys = len(prob.systems)
@@ -93,6 +106,12 @@ def main():
     n_cells = sum(batch.grid_cells(s.grid) for s in prob.systems)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"[bench] {args.config}: {nsys} systems, grid {g.nx}x{g.ny}x{g.nz}")
+    if args.probe_iters > 0:
+        _, _, res = wri.objective_grad(batch, max_iter=args.probe_iters)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe_iters": args.probe_iters, "systems": nsys, "cells_per_system": g.n,
+                          "iters": [r["iters"] for r in res][:4]}))
+        return
 
     for w in range(args.warmup):
         t0 = time.perf_counter()
