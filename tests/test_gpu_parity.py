@@ -449,3 +449,22 @@ def test_uneven_workload_one_launch():
         tr = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d, _np(u[k]), res[k]["alpha"])
         _say(f"  sys {k} (grid {s.grid}): rtol {s.rtol:.1e} iters {res[k]['iters']} true normal residual {tr:.2e}")
         assert tr <= max(3 * s.rtol, 1e-3)
+
+
+def test_estimate_source_entry_point():
+    """estimate_source: on-the-fly source weights (A u)[src] for every system,
+    against the oracle's variable-projection estimate, with and without u_out."""
+    _say("estimate_source")
+    p = wri_synth.custom_problem((30, 26, 22), nb=3, n_src=3, n_rec=10, seed=23, freqs=(5.0, 8.0),
+                                 rtol=PARITY_RTOL, mode="known")   # mode is ignored: always ESTIMATE
+    ref = oracle.objective_grad(p, mode="estimate")
+    b = wri.Batch(p, device=DEV)
+    alpha, res = wri.estimate_source(b, max_iter=60000)
+    u = wri.alloc_wavefields(b)
+    alpha2, res2 = wri.estimate_source(b, max_iter=60000, u_out=u)
+    for k in range(len(p.systems)):
+        e = abs(alpha[k] - ref["alpha"][k]) / abs(ref["alpha"][k])
+        _say(f"  sys {k}: alpha err {e:.2e} iters {res[k]['iters']}")
+        assert e < 1e-4
+        assert alpha2[k] == alpha[k]
+        assert rel(_np(u[k]), ref["u"][k]) < 1e-4
