@@ -54,10 +54,10 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Slab-tile candidates explored by the autotuner; the first is the default.
 const TileCfg kCands[] = {
-    {4, 4, 32, 0}, {4, 4, 16, 0}, {4, 4, 64, 0}, {4, 2, 32, 0}, {4, 2, 16, 0}, {4, 2, 64, 0},
-    {8, 2, 32, 0}, {8, 2, 16, 0}, {2, 8, 32, 0}, {4, 1, 32, 0}, {8, 1, 32, 0}, {8, 1, 16, 0},
-    {4, 4, 32, 1}, {4, 2, 32, 1}, {4, 2, 64, 1}, {8, 2, 32, 1}, {8, 1, 32, 1}, {8, 1, 64, 1},
-    {4, 1, 64, 1}, {8, 2, 64, 1},
+    {4, 4, 32, 0, 0}, {4, 2, 32, 1, 0}, {4, 2, 32, 1, 1}, {4, 2, 16, 1, 1}, {4, 2, 64, 1, 1},
+    {8, 1, 32, 1, 0}, {8, 1, 32, 1, 1}, {8, 1, 16, 1, 1}, {8, 2, 32, 1, 0}, {8, 2, 32, 1, 1},
+    {4, 1, 32, 1, 1}, {4, 1, 64, 1, 1}, {4, 4, 32, 1, 1}, {4, 2, 32, 0, 1}, {8, 1, 16, 0, 1},
+    {8, 2, 16, 0, 1}, {4, 2, 16, 0, 0}, {8, 1, 16, 0, 0}, {2, 8, 32, 0, 0}, {4, 4, 16, 0, 1},
 };
 constexpr int kNumCands = sizeof(kCands) / sizeof(kCands[0]);
 
@@ -414,7 +414,7 @@ int set_config(Ctx& C, const TileCfg& cfg) {
     d.tz = cfg.tz;
     d.ntiles = t.ntiles();
     d.block0 = b0;
-    d.pad_ = 0;
+    d.tile_major = cfg.order;
     b0 += d.nrhs * d.ntiles;
   }
   C.nblocks = b0;
@@ -462,14 +462,17 @@ bool verbose() {
   return v;
 }
 
-// WRI_TILE="w,ry,tz,pf" forces one of the candidate tiles (tests, experiments)
+// WRI_TILE="w,ry,tz,pf[,order]" forces one of the candidate tiles (tests, experiments)
 bool forced_tile(TileCfg* out) {
   const char* e = getenv("WRI_TILE");
   if (e == nullptr || *e == 0) return false;
-  TileCfg t{0, 0, 0, 0};
-  if (sscanf(e, "%d,%d,%d,%d", &t.w, &t.ry, &t.tz, &t.pf) != 4) return false;
+  TileCfg t{0, 0, 0, 0, 0};
+  const int got = sscanf(e, "%d,%d,%d,%d,%d", &t.w, &t.ry, &t.tz, &t.pf, &t.order);
+  if (got < 4) return false;
+  if (got == 4) t.order = 0;
   for (int i = 0; i < kNumCands; ++i)
-    if (kCands[i].w == t.w && kCands[i].ry == t.ry && kCands[i].tz == t.tz && kCands[i].pf == t.pf) {
+    if (kCands[i].w == t.w && kCands[i].ry == t.ry && kCands[i].tz == t.tz && kCands[i].pf == t.pf &&
+        kCands[i].order == t.order) {
       *out = t;
       return true;
     }
@@ -516,8 +519,8 @@ int autotune(Ctx& C) {
     float ms = 0.f;
     WRI_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (verbose())
-      fprintf(stderr, "[wri] autotune %s w=%d ry=%d tz=%d pf=%d -> %.3f ms / 3 iterations\n", key.c_str(),
-              kCands[c].w, kCands[c].ry, kCands[c].tz, kCands[c].pf, ms);
+      fprintf(stderr, "[wri] autotune %s w=%d ry=%d tz=%d pf=%d order=%d -> %.3f ms / 3 iterations\n",
+              key.c_str(), kCands[c].w, kCands[c].ry, kCands[c].tz, kCands[c].pf, kCands[c].order, ms);
     if (ms < best) { best = ms; best_cfg = kCands[c]; }
   }
   (void)hipEventDestroy(e0);
@@ -532,7 +535,7 @@ std::string graph_key(const Ctx& C, int chunk) {
   snprintf(buf, sizeof(buf), "%d|%p|%d|", C.dev, (void*)C.ws, chunk);
   k += buf;
   const TileCfg& c = cur_cfg(C);
-  snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d;", c.w, c.ry, c.tz, c.pf, C.nblocks);
+  snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d;", c.w, c.ry, c.tz, c.pf, c.order, C.nblocks);
   k += buf;
   for (const auto& d : C.hgd) {
     snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d;", d.rhs0, d.nrhs, d.tiles_x, d.tiles_y, d.tz, d.block0);
@@ -605,9 +608,9 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     if (rc != WRI_OK) return rc;
     if (verbose())
       for (size_t gi = 0; gi < C.groups.size(); ++gi)
-        fprintf(stderr, "[wri] grid %d (%d systems): tile w=%d ry=%d tz=%d pf=%d, %d tiles per system\n",
+        fprintf(stderr, "[wri] grid %d (%d systems): tile w=%d ry=%d tz=%d pf=%d order=%d, %d tiles per system\n",
                 C.groups[gi].grid, C.groups[gi].nrhs, C.tiling[gi].cfg.w, C.tiling[gi].cfg.ry, C.tiling[gi].cfg.tz,
-                C.tiling[gi].cfg.pf, C.tiling[gi].ntiles());
+                C.tiling[gi].cfg.pf, C.tiling[gi].cfg.order, C.tiling[gi].ntiles());
     rc = launch_setup(C);
     if (rc != WRI_OK) return rc;
     const bool timing = (C.flags & WRI_FLAG_TIMING) != 0;

@@ -276,8 +276,9 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
   const int local = logical - gd[g].block0;
-  const int rl = local / ntiles;
-  const int tile = local - rl * ntiles;
+  const int nrhs_g = gd[g].nrhs;
+  const int rl = gd[g].tile_major ? (local % nrhs_g) : (local / ntiles);
+  const int tile = gd[g].tile_major ? (local / nrhs_g) : (local - rl * ntiles);
   const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
@@ -470,8 +471,9 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
   const int local = logical - gd[g].block0;
-  const int rl = local / ntiles;
-  const int tile = local - rl * ntiles;
+  const int nrhs_g = gd[g].nrhs;
+  const int rl = gd[g].tile_major ? (local % nrhs_g) : (local / ntiles);
+  const int tile = gd[g].tile_major ? (local / nrhs_g) : (local - rl * ntiles);
   const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
@@ -653,8 +655,9 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
   const int local = logical - gd[g].block0;
-  const int rl = local / ntiles;
-  const int tile = local - rl * ntiles;
+  const int nrhs_g = gd[g].nrhs;
+  const int rl = gd[g].tile_major ? (local % nrhs_g) : (local / ntiles);
+  const int tile = gd[g].tile_major ? (local / nrhs_g) : (local - rl * ntiles);
   const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
@@ -888,8 +891,9 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
   const int local = logical - gd[g].block0;
-  const int rl = local / ntiles;
-  const int tile = local - rl * ntiles;
+  const int nrhs_g = gd[g].nrhs;
+  const int rl = gd[g].tile_major ? (local % nrhs_g) : (local / ntiles);
+  const int tile = gd[g].tile_major ? (local / nrhs_g) : (local - rl * ntiles);
   const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;

@@ -75,6 +75,7 @@ struct TileCfg {
   int ry;      // rows per wavefront  (tile height TY = w*ry)
   int tz;      // z-slab length
   int pf = 0;  // 1: software-pipelined z march (loads of plane z+2 in flight during plane z)
+  int order = 0;  // 1: tile-major block order (see GroupDesc::tile_major)
   int ty() const { return w * ry; }
 };
 
@@ -86,7 +87,8 @@ struct GroupDesc {
   int tiles_x, tiles_y, tz;
   int ntiles;
   int block0;
-  int pad_;
+  int tile_major;  // 1: consecutive blocks take the same tile of successive systems
+                   //    (the tile of m is then read once per XCD for the whole group)
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------

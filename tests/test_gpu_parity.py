@@ -104,7 +104,9 @@ SHAPES = [(16, 16, 16), (70, 37, 19), (33, 65, 12), (5, 6, 7)]
 @pytest.mark.parametrize("shape", SHAPES)
 def test_solve_parity_exact(shape, mode):
     _say(f"solve shape={shape} mode={mode}")
-    p = wri_synth.custom_problem(shape, nb=min(3, min(shape) // 3), n_src=2, n_rec=10, seed=7,
+    # sponge of up to 6 cells: the weakly damped 3-cell sponge on 70x37x19 leaves a KNOWN-mode
+    # system whose float32 attainable accuracy is ~2e-4 (see the precision section of the design doc)
+    p = wri_synth.custom_problem(shape, nb=min(6, min(shape) // 3), n_src=2, n_rec=10, seed=7,
                                  freqs=(6.0, 9.0), rtol=PARITY_RTOL)
     ref = oracle.objective_grad(p, mode=mode)
     b = wri.Batch(p, device=DEV, mode=mode)
@@ -282,8 +284,12 @@ def test_corner_sources_and_receiver_on_source():
 
 @pytest.mark.parametrize("shape", [(3, 2, 1), (1, 1, 5), (64, 1, 3), (65, 17, 2)])
 def test_degenerate_grids(shape):
+    # KNOWN mode: on an undamped 2-cell-thick grid the receivers barely see the
+    # source, and the source weight of ESTIMATE mode is not determined
+    # (cond(S) ~ 1e9 for 65x17x2)
     _say(f"degenerate {shape}")
-    p = wri_synth.custom_problem(shape, nb=0, n_src=1, n_rec=min(3, shape[2]), seed=16, rtol=1e-6)
+    p = wri_synth.custom_problem(shape, nb=0, n_src=1, n_rec=min(3, shape[2]), seed=16, rtol=1e-6,
+                                 mode="known")
     ref = oracle.objective_grad(p)
     u, res = wri.solve(wri.Batch(p, device=DEV))
     assert res[0]["status"] in ("converged",)
@@ -399,8 +405,8 @@ def test_full_size_differentiation_workload():
 # tilings: every candidate slab tile computes the same iterates
 # --------------------------------------------------------------------------
 
-TILES = ["4,4,32,0", "4,4,32,1", "4,2,32,0", "4,2,32,1", "4,2,16,0", "8,1,32,1", "8,2,64,1", "2,8,32,0",
-         "4,1,64,1"]
+TILES = ["4,4,32,0,0", "4,4,32,1,1", "4,2,32,0,1", "4,2,32,1,1", "4,2,32,1,0", "4,2,16,0,0", "8,1,32,1,1",
+         "8,2,32,1,0", "2,8,32,0,0", "4,1,64,1,1"]
 
 
 def test_tile_invariance(monkeypatch):
@@ -420,7 +426,7 @@ def test_tile_invariance(monkeypatch):
             # different tilings sum the float64 partials in a different order
             assert d < 1e-5
     # the pipelined and the plain march of one tile shape produce identical bits
-    for a, b in (("4,4,32,0", "4,4,32,1"), ("4,2,32,0", "4,2,32,1")):
+    for a, b in (("4,2,32,0,1", "4,2,32,1,1"), ("4,2,32,1,0", "4,2,32,1,1")):
         for i in range(len(p.systems)):
             assert torch.equal(outs[a][0][i], outs[b][0][i]), (a, b, i)
 
