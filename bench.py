@@ -35,6 +35,18 @@ HBM_PEAK_GBS = 8000.0
 BYTES_FWD = 52
 BYTES_ADJ = 36
 
+# HBM traffic of one full-batch launch (48 systems x 128^3) from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, median over the launches of a 20-iteration
+# probe), each scaled by what the counter reads for a 1 GiB device copy (FETCH_SIZE x 2.000,
+# WRITE_SIZE x 1.000).  Valid only for the kernel source it was measured on (sha256 prefix);
+# summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
+TRAFFIC = {
+    "kernels_sha256": "46f2a7555a7e72e1",
+    "fwd": {"fetch_kib": 1652400.8, "write_kib": 2359752.5},
+    "adj": {"fetch_kib": 1110978.2, "write_kib": 1573217.3},
+    "fetch_scale": 2.000, "write_scale": 1.000,
+}
+
 
 def _cpu_worker(args):
     """Oracle CGLS (complex128, scipy CSR) on one system for a bounded time."""
@@ -142,18 +154,53 @@ def main():
     kt = wri.kernel_times()
     fwd_gbs = BYTES_FWD * kt["cell_iters"] / (kt["fwd_ms"] * 1e-3) / 1e9
     adj_gbs = BYTES_ADJ * kt["cell_iters"] / (kt["adj_ms"] * 1e-3) / 1e9
-    log(f"[bench] kernels: fwd {kt['fwd_ms'] / kt['fwd_launches']:.3f} ms/launch ({fwd_gbs:.0f} GB/s), "
-        f"adj {kt['adj_ms'] / kt['adj_launches']:.3f} ms/launch ({adj_gbs:.0f} GB/s)")
+    cells_full = kt["cells_per_launch_full"]
+    fwd_full_ms = kt["fwd_ms_full"] / max(1, kt["fwd_launches_full"])
+    adj_full_ms = kt["adj_ms_full"] / max(1, kt["adj_launches_full"])
+    fwd_full_gbs = BYTES_FWD * cells_full / (fwd_full_ms * 1e-3) / 1e9
+    adj_full_gbs = BYTES_ADJ * cells_full / (adj_full_ms * 1e-3) / 1e9
+    log(f"[bench] kernels (all launches): fwd {kt['fwd_ms'] / kt['fwd_launches']:.3f} ms ({fwd_gbs:.0f} GB/s), "
+        f"adj {kt['adj_ms'] / kt['adj_launches']:.3f} ms ({adj_gbs:.0f} GB/s); full batch: fwd "
+        f"{fwd_full_ms:.3f} ms ({fwd_full_gbs:.0f} GB/s), adj {adj_full_ms:.3f} ms ({adj_full_gbs:.0f} GB/s)")
     dominant = "fwd" if kt["fwd_ms"] >= kt["adj_ms"] else "adj"
     ach = fwd_gbs if dominant == "fwd" else adj_gbs
+    ach_full = fwd_full_gbs if dominant == "fwd" else adj_full_gbs
+    bper = BYTES_FWD if dominant == "fwd" else BYTES_ADJ
+    traffic = None
+    with open(os.path.join(ROOT, "paper_2410_18429_amd", "csrc", "kernels.hip"), "rb") as f:
+        import hashlib
+        same_kernels = hashlib.sha256(f.read()).hexdigest()[:16] == TRAFFIC["kernels_sha256"]
+    if same_kernels and args.config == "differentiation":
+        tr = TRAFFIC[dominant]
+        traffic = round(1024.0 * (tr["fetch_kib"] * TRAFFIC["fetch_scale"] + tr["write_kib"] * TRAFFIC["write_scale"]))
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_fwd (fused forward CGLS stencil)" if dominant == "fwd" else
-                          "k_adj (fused adjoint CGLS stencil)",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "HBM bytes per full-batch launch",
+                "algorithmic_bytes_full_launch": bper * cells_full,
+                "kernel": "k_fwd / k_fwd_pf (fused forward CGLS stencil)" if dominant == "fwd" else
+                          "k_adj / k_adj_pf (fused adjoint CGLS stencil)",
                 "avg_launch_ms": round((kt["fwd_ms"] / kt["fwd_launches"]) if dominant == "fwd"
                                        else (kt["adj_ms"] / kt["adj_launches"]), 4),
+                "achieved_full_batch": round(ach_full, 1),
+                "frac_full_batch": round(ach_full / HBM_PEAK_GBS, 4),
+                "avg_launch_ms_full_batch": round(fwd_full_ms if dominant == "fwd" else adj_full_ms, 4),
                 "fwd_gbs": round(fwd_gbs, 1), "adj_gbs": round(adj_gbs, 1),
+                "fwd_gbs_full_batch": round(fwd_full_gbs, 1), "adj_gbs_full_batch": round(adj_full_gbs, 1),
                 "bytes_per_cell_iter": {"fwd": BYTES_FWD, "adj": BYTES_ADJ}}
+
+    # practical ceiling on this machine: a plain device-to-device copy of 2 GiB
+    nc = (2 << 30) // 4
+    csrc = torch.ones(nc, dtype=torch.float32, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        cdst.copy_(csrc)
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * 4 * nc / (time.perf_counter() - t0) / 1e9
+    roofline["copy_gbs"] = round(copy_gbs, 1)
+    del csrc, cdst
 
     plain = None
     if not args.no_plain and args.plain_sample > 0:

@@ -197,13 +197,20 @@ int estimate_source(const wri_grid* grids, int32_t n_grids, const float* const* 
 int wri_apply_helmholtz(const wri_grid* grid, const float* m, double omega,
                         const wri_c32* in, wri_c32* out, int32_t adjoint, void* stream);
 
-/* Kernel time of the last WRI_FLAG_TIMING call on this thread: summed
- * durations [ms] and launch counts of the fused forward and adjoint launches
- * (one launch covers every active system of one grid), and the number of
- * (system, cell) updates each kind performed in full.  Returns WRI_EINVAL if
- * no timed call has run on this thread. */
-int wri_kernel_times(double* fwd_ms, int64_t* fwd_launches, double* adj_ms, int64_t* adj_launches,
-                     int64_t* cell_iters);
+/* Kernel time of the last WRI_FLAG_TIMING call on this thread (HIP event
+ * pairs around every fused launch; one launch covers every active system). */
+typedef struct {
+  double  fwd_ms, adj_ms;                /* summed durations of the fused launches       */
+  int64_t fwd_launches, adj_launches;
+  int64_t cell_iters;                    /* sum over systems of cells x iterations       */
+  double  fwd_ms_full, adj_ms_full;      /* the launches during which every system was
+                                            still iterating (whole batch resident)       */
+  int64_t fwd_launches_full, adj_launches_full;
+  int64_t cells_per_launch_full;         /* cells of all systems in one such launch      */
+} wri_timing;
+
+/* Fills *out; WRI_EINVAL if no timed call has completed on this thread. */
+int wri_kernel_times(wri_timing* out);
 
 /* Text of a return code; message of the last error on this thread. */
 const char* wri_strerror(int code);

@@ -26,8 +26,7 @@ thread_local std::string g_last_error;
 
 struct KernelTimes {
   bool valid = false;
-  double fwd_ms = 0.0, adj_ms = 0.0;
-  int64_t fwd_n = 0, adj_n = 0, cell_iters = 0;
+  wri_timing t{};
 };
 thread_local KernelTimes g_times;
 
@@ -644,11 +643,22 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
       rc = read_states(C, hs);
       if (rc != WRI_OK) return rc;
       if (timing) {
+        bool all_active = true;
+        for (const auto& st : hs) all_active = all_active && (st.status == kActive);
         float ms = 0.f;
-        for (auto& e : ev_fwd) { WRI_HIP(hipEventElapsedTime(&ms, e.first, e.second)); g_times.fwd_ms += ms; }
-        for (auto& e : ev_adj) { WRI_HIP(hipEventElapsedTime(&ms, e.first, e.second)); g_times.adj_ms += ms; }
-        g_times.fwd_n += (int64_t)ev_fwd.size();
-        g_times.adj_n += (int64_t)ev_adj.size();
+        wri_timing& T = g_times.t;
+        for (auto& e : ev_fwd) {
+          WRI_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+          T.fwd_ms += ms;
+          if (all_active) { T.fwd_ms_full += ms; T.fwd_launches_full++; }
+        }
+        for (auto& e : ev_adj) {
+          WRI_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+          T.adj_ms += ms;
+          if (all_active) { T.adj_ms_full += ms; T.adj_launches_full++; }
+        }
+        T.fwd_launches += (int64_t)ev_fwd.size();
+        T.adj_launches += (int64_t)ev_adj.size();
       }
       bool active = false;
       for (const auto& s : hs) active = active || (s.status == kActive);
@@ -659,12 +669,14 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     }
   }
   if (C.flags & WRI_FLAG_TIMING) {
-    int64_t ci = 0;
+    int64_t ci = 0, cl = 0;
     for (int p = 0; p < C.n_sys; ++p) {
       const wri_grid& g = C.grids[C.sys[L.order[p]].grid];
       ci += cells(g) * (int64_t)hs[p].iters;
+      cl += cells(g);
     }
-    g_times.cell_iters = ci;
+    g_times.t.cell_iters = ci;
+    g_times.t.cells_per_launch_full = cl;
     g_times.valid = true;
   }
   // objective partials and gradient, per grid
@@ -957,17 +969,12 @@ const char* wri_strerror(int code) {
 
 const char* wri_last_error(void) { return g_last_error.c_str(); }
 
-int wri_kernel_times(double* fwd_ms, int64_t* fwd_launches, double* adj_ms, int64_t* adj_launches,
-                     int64_t* cell_iters) {
+int wri_kernel_times(wri_timing* out) {
   if (!g_times.valid) return fail(WRI_EINVAL, "no WRI_FLAG_TIMING call has completed on this thread");
-  if (fwd_ms) *fwd_ms = g_times.fwd_ms;
-  if (fwd_launches) *fwd_launches = g_times.fwd_n;
-  if (adj_ms) *adj_ms = g_times.adj_ms;
-  if (adj_launches) *adj_launches = g_times.adj_n;
-  if (cell_iters) *cell_iters = g_times.cell_iters;
+  if (out == nullptr) return fail(WRI_EINVAL, "out is NULL");
+  *out = g_times.t;
   return WRI_OK;
 }
-
 int wri_version(void) { return 100; }
 
 }  // extern "C"

@@ -62,6 +62,13 @@ class WriResult(ctypes.Structure):
                 ("alpha", WriC64), ("alpha_ls", WriC64)]
 
 
+class WriTiming(ctypes.Structure):
+    _fields_ = [("fwd_ms", c_double), ("adj_ms", c_double), ("fwd_launches", ctypes.c_int64),
+                ("adj_launches", ctypes.c_int64), ("cell_iters", ctypes.c_int64), ("fwd_ms_full", c_double),
+                ("adj_ms_full", c_double), ("fwd_launches_full", ctypes.c_int64),
+                ("adj_launches_full", ctypes.c_int64), ("cells_per_launch_full", ctypes.c_int64)]
+
+
 class WriError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"wri error {code}: {msg}")
@@ -103,8 +110,7 @@ def lib() -> ctypes.CDLL:
     L.wri_last_error.restype = ctypes.c_char_p
     L.wri_version.argtypes = []
     L.wri_version.restype = c_int
-    L.wri_kernel_times.argtypes = [POINTER(c_double), POINTER(ctypes.c_int64), POINTER(c_double),
-                                   POINTER(ctypes.c_int64), POINTER(ctypes.c_int64)]
+    L.wri_kernel_times.argtypes = [POINTER(WriTiming)]
     L.wri_kernel_times.restype = c_int
     _lib = L
     return L
@@ -116,12 +122,9 @@ EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_objective_g
 
 def kernel_times() -> dict:
     """Totals of the last FLAG_TIMING call on this thread."""
-    f, a = c_double(0), c_double(0)
-    nf, na, ci = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
-    _check(lib().wri_kernel_times(ctypes.byref(f), ctypes.byref(nf), ctypes.byref(a), ctypes.byref(na),
-                                  ctypes.byref(ci)))
-    return dict(fwd_ms=f.value, fwd_launches=nf.value, adj_ms=a.value, adj_launches=na.value,
-                cell_iters=ci.value)
+    t = WriTiming()
+    _check(lib().wri_kernel_times(ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in WriTiming._fields_}
 
 
 def last_error() -> str:
