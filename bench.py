@@ -29,11 +29,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "src·freq augmented solves/s at 128³, rtol 1e-4: batched vs plain; stencil GB/s"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per (system, cell) of one fused launch (complex64 = 8 B, m = 4 B):
-#   forward: read s, p_{k-1}, x, m; write p_k, t, x          -> 8*3 + 4 + 8*3 = 52
-#   adjoint: read r_k, t, m; write r_{k+1}, s                  -> 8*2 + 4 + 8*2 = 36
-BYTES_FWD = 52
-BYTES_ADJ = 36
+# Algorithmic bytes per (system, cell) of one fused launch (complex64 = 8 B, m = 4 B), as
+# the library counts them for every timed launch:
+#   forward k: read s, p_{k-1}, m; write p_k, t                          -> 36
+#              + on even k >= 2: read x, p_{k-2}; write x               -> +24
+#   adjoint k: read r_k, t, m; write r_{k+1}, s                         -> 36
+BYTES_NOTE = {"fwd": "36, +24 on even iterations (x update of two steps)", "adj": "36"}
 
 # HBM traffic of one full-batch launch (48 systems x 128^3) from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, median over the launches of a 20-iteration
@@ -94,7 +95,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(systems are independent; see DESIGN.md for how the batch would shard).", file=sys.stderr)
+              "(the systems are independent: a batch would shard by system across GPUs).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -152,20 +153,20 @@ def main():
     wri.objective_grad(batch, flags=wri.FLAG_TIMING)
     torch.cuda.synchronize()
     kt = wri.kernel_times()
-    fwd_gbs = BYTES_FWD * kt["cell_iters"] / (kt["fwd_ms"] * 1e-3) / 1e9
-    adj_gbs = BYTES_ADJ * kt["cell_iters"] / (kt["adj_ms"] * 1e-3) / 1e9
-    cells_full = kt["cells_per_launch_full"]
+    fwd_gbs = kt["fwd_bytes"] / (kt["fwd_ms"] * 1e-3) / 1e9
+    adj_gbs = kt["adj_bytes"] / (kt["adj_ms"] * 1e-3) / 1e9
     fwd_full_ms = kt["fwd_ms_full"] / max(1, kt["fwd_launches_full"])
     adj_full_ms = kt["adj_ms_full"] / max(1, kt["adj_launches_full"])
-    fwd_full_gbs = BYTES_FWD * cells_full / (fwd_full_ms * 1e-3) / 1e9
-    adj_full_gbs = BYTES_ADJ * cells_full / (adj_full_ms * 1e-3) / 1e9
+    fwd_full_bytes = kt["fwd_bytes_full"] / max(1, kt["fwd_launches_full"])
+    adj_full_bytes = kt["adj_bytes_full"] / max(1, kt["adj_launches_full"])
+    fwd_full_gbs = fwd_full_bytes / (fwd_full_ms * 1e-3) / 1e9
+    adj_full_gbs = adj_full_bytes / (adj_full_ms * 1e-3) / 1e9
     log(f"[bench] kernels (all launches): fwd {kt['fwd_ms'] / kt['fwd_launches']:.3f} ms ({fwd_gbs:.0f} GB/s), "
         f"adj {kt['adj_ms'] / kt['adj_launches']:.3f} ms ({adj_gbs:.0f} GB/s); full batch: fwd "
         f"{fwd_full_ms:.3f} ms ({fwd_full_gbs:.0f} GB/s), adj {adj_full_ms:.3f} ms ({adj_full_gbs:.0f} GB/s)")
     dominant = "fwd" if kt["fwd_ms"] >= kt["adj_ms"] else "adj"
     ach = fwd_gbs if dominant == "fwd" else adj_gbs
     ach_full = fwd_full_gbs if dominant == "fwd" else adj_full_gbs
-    bper = BYTES_FWD if dominant == "fwd" else BYTES_ADJ
     traffic = None
     with open(os.path.join(ROOT, "paper_2410_18429_amd", "csrc", "kernels.hip"), "rb") as f:
         import hashlib
@@ -176,7 +177,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per full-batch launch",
-                "algorithmic_bytes_full_launch": bper * cells_full,
+                "algorithmic_bytes_full_launch": round(fwd_full_bytes if dominant == "fwd" else adj_full_bytes),
                 "kernel": "k_fwd / k_fwd_pf (fused forward CGLS stencil)" if dominant == "fwd" else
                           "k_adj / k_adj_pf (fused adjoint CGLS stencil)",
                 "avg_launch_ms": round((kt["fwd_ms"] / kt["fwd_launches"]) if dominant == "fwd"
@@ -186,21 +187,7 @@ def main():
                 "avg_launch_ms_full_batch": round(fwd_full_ms if dominant == "fwd" else adj_full_ms, 4),
                 "fwd_gbs": round(fwd_gbs, 1), "adj_gbs": round(adj_gbs, 1),
                 "fwd_gbs_full_batch": round(fwd_full_gbs, 1), "adj_gbs_full_batch": round(adj_full_gbs, 1),
-                "bytes_per_cell_iter": {"fwd": BYTES_FWD, "adj": BYTES_ADJ}}
-
-    # practical ceiling on this machine: a plain device-to-device copy of 2 GiB
-    nc = (2 << 30) // 4
-    csrc = torch.ones(nc, dtype=torch.float32, device=dev)
-    cdst = torch.empty_like(csrc)
-    cdst.copy_(csrc)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(10):
-        cdst.copy_(csrc)
-    torch.cuda.synchronize()
-    copy_gbs = 10 * 2 * 4 * nc / (time.perf_counter() - t0) / 1e9
-    roofline["copy_gbs"] = round(copy_gbs, 1)
-    del csrc, cdst
+                "bytes_per_cell": BYTES_NOTE}
 
     plain = None
     if not args.no_plain and args.plain_sample > 0:

@@ -69,7 +69,8 @@ extern "C" {
 typedef struct { float re, im; } wri_c32;
 typedef struct { double re, im; } wri_c64;
 
-/* One grid. nx*ny*nz < 2^31 cells; h > 0 [m]; nb >= 0 sponge cells;
+/* One grid. nx*ny*nz < 2^31 cells and nx*ny <= 3834792 cells per x-y plane
+ * (70 planes of complex64 addressable with 32-bit offsets); h > 0 [m]; nb >= 0 sponge cells;
  * v_ref > 0 [m/s] (sponge reference velocity; ignored when nb == 0). */
 typedef struct {
   int32_t nx, ny, nz;
@@ -198,15 +199,17 @@ int wri_apply_helmholtz(const wri_grid* grid, const float* m, double omega,
                         const wri_c32* in, wri_c32* out, int32_t adjoint, void* stream);
 
 /* Kernel time of the last WRI_FLAG_TIMING call on this thread (HIP event
- * pairs around every fused launch; one launch covers every active system). */
+ * pairs around every fused launch; one launch covers every active system).
+ * Bytes are algorithmic: per cell, forward 36 B (+24 B for the x update on
+ * even iterations k >= 2), adjoint 36 B; halo re-reads are not counted. */
 typedef struct {
   double  fwd_ms, adj_ms;                /* summed durations of the fused launches       */
   int64_t fwd_launches, adj_launches;
-  int64_t cell_iters;                    /* sum over systems of cells x iterations       */
+  double  fwd_bytes, adj_bytes;          /* algorithmic bytes of those launches          */
   double  fwd_ms_full, adj_ms_full;      /* the launches during which every system was
                                             still iterating (whole batch resident)       */
   int64_t fwd_launches_full, adj_launches_full;
-  int64_t cells_per_launch_full;         /* cells of all systems in one such launch      */
+  double  fwd_bytes_full, adj_bytes_full;
 } wri_timing;
 
 /* Fills *out; WRI_EINVAL if no timed call has completed on this thread. */

@@ -24,6 +24,17 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Algorithmic HBM bytes per cell of the fused launches (complex64 vectors,
+// float32 model), the figures the roofline is quoted on.
+//   forward k: reads s, p_{k-1}, m; writes p_k, t                       36 B
+//              + at even k >= 2 reads x, p_{k-2} and writes x           24 B
+//   adjoint k: reads r_k, t, m; writes r_{k+1}, s                       36 B
+// Halo re-reads and the receiver rows are not counted.
+constexpr int kFwdBytesPerCell = 36, kFwdXBytesPerCell = 24, kAdjBytesPerCell = 36;
+inline int fwd_bytes_per_cell(int64_t k) {
+  return kFwdBytesPerCell + ((k >= 2 && (k & 1) == 0) ? kFwdXBytesPerCell : 0);
+}
+
 struct KernelTimes {
   bool valid = false;
   wri_timing t{};
@@ -87,6 +98,8 @@ int64_t cells(const wri_grid& g) { return (int64_t)g.nx * g.ny * g.nz; }
 // validation (host only)
 // ---------------------------------------------------------------------------
 
+constexpr int64_t kMaxPlaneSpan = 70;  // planes one slab's buffer resources may span (z-slab <= 64, + halo)
+
 int validate(const wri_grid* grids, int32_t n_grids, const wri_system* sys, int32_t n_sys, int32_t mode,
              int32_t max_iter) {
   if (n_grids < 0 || n_sys < 0) return fail(WRI_EINVAL, "negative n_grids or n_sys");
@@ -98,6 +111,10 @@ int validate(const wri_grid* grids, int32_t n_grids, const wri_system* sys, int3
     const wri_grid& g = grids[i];
     if (g.nx < 1 || g.ny < 1 || g.nz < 1) return fail(WRI_EINVAL, "grid %d: non-positive size", i);
     if (cells(g) >= (int64_t(1) << 31)) return fail(WRI_EINVAL, "grid %d: more than 2^31-1 cells", i);
+    // the fused kernels address up to 70 planes of complex64 with 32-bit byte offsets
+    if ((int64_t)g.nx * g.ny * kMaxPlaneSpan * 8 >= (int64_t(1) << 31))
+      return fail(WRI_EINVAL, "grid %d: more than %lld cells in one x-y plane", i,
+                  (long long)(((int64_t(1) << 31) - 1) / (kMaxPlaneSpan * 8)));
     if (!(g.h > 0.0) || !std::isfinite(g.h)) return fail(WRI_EINVAL, "grid %d: h must be > 0", i);
     if (g.nb < 0) return fail(WRI_EINVAL, "grid %d: nb < 0", i);
     if (g.nb > 0 && (!(g.v_ref > 0.0) || !std::isfinite(g.v_ref)))
@@ -427,14 +444,15 @@ int set_config(Ctx& C, const TileCfg& cfg) {
 const TileCfg& cur_cfg(const Ctx& C) { return C.tiling.front().cfg; }
 
 // eager iteration with an event pair around the forward and adjoint launches
-int launch_iteration_timed(Ctx& C, EventPool& pool, std::vector<std::pair<hipEvent_t, hipEvent_t>>& fwd,
+int launch_iteration_timed(Ctx& C, int k, EventPool& pool, std::vector<std::pair<hipEvent_t, hipEvent_t>>& fwd,
                            std::vector<std::pair<hipEvent_t, hipEvent_t>>& adj) {
   for (int phase = 0; phase < 2; ++phase) {
     hipEvent_t a = pool.next(), b = pool.next();
     if (!a || !b) return fail(WRI_EHIP, "hipEventCreate failed");
     WRI_HIP(hipEventRecord(a, C.st));
     if (phase == 0)
-      WRI_HIP(launch_fwd(cur_cfg(C), C.dsys, C.dstate, C.part_s, C.part_d, C.dgd, (int)C.hgd.size(), C.nblocks, C.st));
+      WRI_HIP(launch_fwd(cur_cfg(C), C.dsys, C.dstate, C.part_s, C.part_d, C.dgd, (int)C.hgd.size(), C.nblocks, k,
+                         C.st));
     else
       WRI_HIP(launch_adj(cur_cfg(C), C.dsys, C.dstate, C.part_d, C.part_s, C.dgd, (int)C.hgd.size(), C.nblocks, C.st));
     WRI_HIP(hipEventRecord(b, C.st));
@@ -443,9 +461,9 @@ int launch_iteration_timed(Ctx& C, EventPool& pool, std::vector<std::pair<hipEve
   return WRI_OK;
 }
 
-// one CGLS iteration: the forward launch then the adjoint launch, each over all groups
-int launch_iteration(Ctx& C, hipStream_t s) {
-  WRI_HIP(launch_fwd(cur_cfg(C), C.dsys, C.dstate, C.part_s, C.part_d, C.dgd, (int)C.hgd.size(), C.nblocks, s));
+// CGLS iteration k: the forward launch then the adjoint launch, each over all groups
+int launch_iteration(Ctx& C, int k, hipStream_t s) {
+  WRI_HIP(launch_fwd(cur_cfg(C), C.dsys, C.dstate, C.part_s, C.part_d, C.dgd, (int)C.hgd.size(), C.nblocks, k, s));
   WRI_HIP(launch_adj(cur_cfg(C), C.dsys, C.dstate, C.part_d, C.part_s, C.dgd, (int)C.hgd.size(), C.nblocks, s));
   return WRI_OK;
 }
@@ -508,17 +526,17 @@ int autotune(Ctx& C) {
   for (int c = 0; c < kNumCands; ++c) {
     int rc = set_config(C, kCands[c]);
     if (rc == WRI_OK) rc = launch_setup(C);
-    if (rc == WRI_OK) rc = launch_iteration(C, C.st);  // warm
+    if (rc == WRI_OK) rc = launch_iteration(C, 0, C.st);  // warm
     if (rc != WRI_OK) return rc;
     WRI_HIP(hipEventRecord(e0, C.st));
-    for (int it2 = 0; it2 < 3 && rc == WRI_OK; ++it2) rc = launch_iteration(C, C.st);
+    for (int it2 = 1; it2 <= 4 && rc == WRI_OK; ++it2) rc = launch_iteration(C, it2, C.st);
     if (rc != WRI_OK) return rc;
     WRI_HIP(hipEventRecord(e1, C.st));
     WRI_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     WRI_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (verbose())
-      fprintf(stderr, "[wri] autotune %s w=%d ry=%d tz=%d pf=%d order=%d -> %.3f ms / 3 iterations\n",
+      fprintf(stderr, "[wri] autotune %s w=%d ry=%d tz=%d pf=%d order=%d -> %.3f ms / 4 iterations\n",
               key.c_str(), kCands[c].w, kCands[c].ry, kCands[c].tz, kCands[c].pf, kCands[c].order, ms);
     if (ms < best) { best = ms; best_cfg = kCands[c]; }
   }
@@ -528,10 +546,11 @@ int autotune(Ctx& C) {
   return set_config(C, best_cfg);
 }
 
-std::string graph_key(const Ctx& C, int chunk) {
+std::string graph_key(const Ctx& C, int64_t k0, int chunk) {
   std::string k;
   char buf[128];
-  snprintf(buf, sizeof(buf), "%d|%p|%d|", C.dev, (void*)C.ws, chunk);
+  // the kernels of a chunk depend on k0 only through fwd_x_step(k0 + i)
+  snprintf(buf, sizeof(buf), "%d|%p|%d|%d|%d|", C.dev, (void*)C.ws, chunk, (int)(k0 & 1), k0 >= 2 ? 1 : (int)k0);
   k += buf;
   const TileCfg& c = cur_cfg(C);
   snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d;", c.w, c.ry, c.tz, c.pf, c.order, C.nblocks);
@@ -543,8 +562,8 @@ std::string graph_key(const Ctx& C, int chunk) {
   return k;
 }
 
-int get_graph(Ctx& C, int chunk, hipGraphExec_t* out) {
-  const std::string key = graph_key(C, chunk);
+int get_graph(Ctx& C, int64_t k0, int chunk, hipGraphExec_t* out) {
+  const std::string key = graph_key(C, k0, chunk);
   auto it = g_graphs.find(key);
   if (it != g_graphs.end()) { *out = it->second.exec; return WRI_OK; }
   hipStream_t cs = capture_stream(C.dev);
@@ -552,7 +571,7 @@ int get_graph(Ctx& C, int chunk, hipGraphExec_t* out) {
   GraphEntry e;
   WRI_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   int rc = WRI_OK;
-  for (int i = 0; i < chunk && rc == WRI_OK; ++i) rc = launch_iteration(C, cs);
+  for (int i = 0; i < chunk && rc == WRI_OK; ++i) rc = launch_iteration(C, (int)(k0 + i), cs);
   hipGraph_t graph = nullptr;
   hipError_t ec = hipStreamEndCapture(cs, &graph);
   if (rc != WRI_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
@@ -625,20 +644,21 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
         ev_fwd.clear();
         ev_adj.clear();
         for (int i = 0; i < chunk; ++i) {
-          rc = launch_iteration_timed(C, pool, ev_fwd, ev_adj);
+          rc = launch_iteration_timed(C, (int)(launched + i), pool, ev_fwd, ev_adj);
           if (rc != WRI_OK) return rc;
         }
       } else if (use_graph) {
         hipGraphExec_t ex = nullptr;
-        rc = get_graph(C, chunk, &ex);
+        rc = get_graph(C, launched, chunk, &ex);
         if (rc != WRI_OK) return rc;
         WRI_HIP(hipGraphLaunch(ex, C.st));
       } else {
         for (int i = 0; i < chunk; ++i) {
-          rc = launch_iteration(C, C.st);
+          rc = launch_iteration(C, (int)(launched + i), C.st);
           if (rc != WRI_OK) return rc;
         }
       }
+      const int64_t kstart = launched;
       launched += chunk;
       rc = read_states(C, hs);
       if (rc != WRI_OK) return rc;
@@ -647,6 +667,21 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
         for (const auto& st : hs) all_active = all_active && (st.status == kActive);
         float ms = 0.f;
         wri_timing& T = g_times.t;
+        // algorithmic bytes of each launch of the chunk: a system takes part in
+        // launch k with full work while k < its final iteration count
+        for (int i = 0; i < chunk; ++i) {
+          const int64_t k = kstart + i;
+          double fb = 0.0, ab = 0.0;
+          for (int p = 0; p < C.n_sys; ++p) {
+            if (hs[p].status != kActive && hs[p].iters <= k) continue;
+            const double n = (double)cells(C.grids[C.sys[L.order[p]].grid]);
+            fb += n * (double)fwd_bytes_per_cell(k);
+            ab += n * (double)kAdjBytesPerCell;
+          }
+          T.fwd_bytes += fb;
+          T.adj_bytes += ab;
+          if (all_active) { T.fwd_bytes_full += fb; T.adj_bytes_full += ab; }
+        }
         for (auto& e : ev_fwd) {
           WRI_HIP(hipEventElapsedTime(&ms, e.first, e.second));
           T.fwd_ms += ms;
@@ -668,17 +703,7 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
       chunk = std::min(chunk * 2, 128);
     }
   }
-  if (C.flags & WRI_FLAG_TIMING) {
-    int64_t ci = 0, cl = 0;
-    for (int p = 0; p < C.n_sys; ++p) {
-      const wri_grid& g = C.grids[C.sys[L.order[p]].grid];
-      ci += cells(g) * (int64_t)hs[p].iters;
-      cl += cells(g);
-    }
-    g_times.t.cell_iters = ci;
-    g_times.t.cells_per_launch_full = cl;
-    g_times.valid = true;
-  }
+  if (C.flags & WRI_FLAG_TIMING) g_times.valid = true;
   // objective partials and gradient, per grid
   for (int g = 0; g < C.n_grids; ++g) {
     const Group* G = nullptr;

@@ -6,7 +6,9 @@
 // ("GPU acceleration" section).  Each iteration is two fused, bandwidth-bound
 // launches over every active system:
 //
-//   fwd (k):  x += a_{k-1} p_{k-1};  p_k = s_k + beta_k p_{k-1};
+//   fwd (k):  p_k = s_k + beta_k p_{k-1};  on even k >= 2 (and when the
+//             system stops) x += a_{k-2} p_{k-2} + a_{k-1} p_{k-1}, the two
+//             pending steps (p_{k-2} still sits in the buffer p_k overwrites);
 //             t = S p_k (7-point stencil + source column + receiver gather);
 //             float64 partials of ||t||^2.
 //   adj (k):  a_k = gamma_k / ||t||^2;  r_{k+1} = r_k - a_k t;
@@ -51,6 +53,13 @@ __device__ __forceinline__ float2 ld2(const GLOBAL float2* p, int i) {
 }
 __device__ __forceinline__ void st2(GLOBAL float2* p, int i, float2 v) {
   *((GLOBAL unsigned long long*)p + i) = __builtin_bit_cast(unsigned long long, v);
+}
+// Stores of values that no other workgroup reads in the same launch (every
+// output of the fused kernels) carry the non-temporal hint: measured about
+// 1.5 % faster on the forward kernel and 1 % on the adjoint.  (The same hint on
+// loads of halo-free inputs was slower.)
+__device__ __forceinline__ void st2s(GLOBAL float2* p, int i, float2 v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), (GLOBAL unsigned long long*)p + i);
 }
 __device__ __forceinline__ int2 ld2i(const GLOBAL int2* p, int i) {
   return __builtin_bit_cast(int2, *((const GLOBAL unsigned long long*)p + i));
@@ -140,6 +149,12 @@ __device__ __forceinline__ float2 f2(float a, float b) { return make_float2(a, b
 __device__ __forceinline__ float2 axpy2(float2 y, double a, float2 x) {
   return f2((float)((double)y.x + a * (double)x.x), (float)((double)y.y + a * (double)x.y));
 }
+// x + c2 p2 + c1 p1 in float64 arithmetic, rounded once (the x update that
+// takes two CGLS steps at a time; with c2 = 0 it equals axpy2(x, c1, p1))
+__device__ __forceinline__ float2 xupd2(float2 x, double c2, float2 p2, double c1, float2 p1) {
+  return f2((float)(((double)x.x + c2 * (double)p2.x) + c1 * (double)p1.x),
+            (float)(((double)x.y + c2 * (double)p2.y) + c1 * (double)p1.y));
+}
 __device__ __forceinline__ double norm2d(float2 v) {
   return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
 }
@@ -182,6 +197,7 @@ __global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, S
       T->iterB = -1;
       T->status = kActive;
       T->iters = 0;
+      T->brk = 0;
     }
   }
 }
@@ -288,9 +304,17 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   const double gk = block_sum_slots<W>(part_s + S.slot_base, ntiles, red);
   const double g0 = (k == 0) ? gk : T->gamma0;
   const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
-  const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
+  // brk: the adjoint launch of this same k broke down; this launch only finishes x
+  const bool brk = T->brk != 0;
+  const bool stop = brk || (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
   const double beta = (k == 0) ? 0.0 : gk / T->gamma[(k - 1) & 1];
   const double aprev = (k == 0) ? 0.0 : T->a[(k - 1) & 1];
+  // x takes the pending steps on even iterations and when the system stops:
+  // c1 p_{k-1} (+ c2 p_{k-2} at even k >= 2; a_{k-2} is still in a[k & 1]).
+  // After a breakdown this k already ran once: only an odd k left a step pending.
+  const bool xstep = brk ? (k & 1) == 1 : stop ? (k >= 1) : (k >= 2 && (k & 1) == 0);
+  const double c1 = xstep ? aprev : 0.0;
+  const double c2 = (xstep && !brk && k >= 2 && (k & 1) == 0) ? T->a[k & 1] : 0.0;
   if (tile == 0 && tid == 0) {
     T->gamma[k & 1] = gk;
     T->gmin[k & 1] = fmin(gmin, gk);
@@ -301,7 +325,6 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   Ctx C;
   C.setup(S, tile, lane, w, tiles_x, tiles_y, tz);
   const int plane = C.plane;
-  const double af = aprev;
   const double bf = beta;
   const double w2 = S.omega_d * S.omega_d;
   const GLOBAL float2* __restrict__ sv = gptr((const float2*)S.s);
@@ -323,17 +346,18 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   }
 
   if (stop) {
-    // finish x with the last step; the adjoint kernel records the status
-    if (aprev != 0.0) {
+    // finish x with the pending steps; the adjoint kernel records the status
+    if (xstep) {
       for (int z = C.z0; z < C.z1; ++z) {
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
           if (!C.in[j]) continue;
           const int c = z * plane + C.gy[j] * S.nx + C.gx;
-          st2(xv, c, axpy2(ld2(xv, c), af, ld2(po, c)));
+          const float2 p2 = (c2 != 0.0) ? ld2(pn, c) : f2(0.f, 0.f);
+          st2s(xv, c, xupd2(ld2(xv, c), c2, p2, c1, ld2(po, c)));
         }
       }
-      if (srcj >= 0) {
+      if (srcj >= 0 && !brk) {
         const double2 pa = T->pa;
         T->xa = make_double2(T->xa.x + aprev * pa.x, T->xa.y + aprev * pa.y);
       }
@@ -430,9 +454,12 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
         td.y -= S.alpha_c * pa_new.y;
       }
       const float2 tv = round2(td);
-      st2(tout, c, tv);
-      st2(pn, c, pc[j]);
-      if (aprev != 0.0) st2(xv, c, axpy2(ld2(xv, c), af, poc[j]));
+      if (xstep) {  // read p_{k-2} before p_k replaces it
+        const float2 p2 = (c2 != 0.0) ? ld2(pn, c) : f2(0.f, 0.f);
+        st2s(xv, c, xupd2(ld2(xv, c), c2, p2, c1, poc[j]));
+      }
+      st2s(tout, c, tv);
+      st2s(pn, c, pc[j]);
       acc += norm2d(tv);
       while (rc.nz_[j] == z) {
         const int q = rc.take(S, j);
@@ -487,10 +514,12 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
     const double gk = T->gamma[k & 1];
     const double g0 = T->gamma0;
     const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
-    const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
+    const bool brk = T->brk != 0;
+    const bool stop = brk || (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
     if (stop) {
       if (tile == 0 && tid == 0) {
-        T->status = (g0 == 0.0) ? kZeroRhs
+        T->status = brk ? kBreakdown
+                  : (g0 == 0.0) ? kZeroRhs
                   : (gk <= S.rtol2 * g0) ? kConverged
                   : (gk > kDivergeRatio * gmin) ? kDiverged : kMaxIter;
         T->iters = k;
@@ -499,10 +528,9 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
     }
     const double dk = block_sum_slots<W>(part_d + S.slot_base, ntiles, red);
     if (!(dk > 0.0) || !(dk <= DBL_MAX) || !(gk <= DBL_MAX)) {
-      if (tile == 0 && tid == 0) {
-        T->status = kBreakdown;
-        T->iters = k;
-      }
+      // x may still lack a step: the next forward launch (same k) finishes it
+      // and the adjoint launch after it records the status
+      if (tile == 0 && tid == 0) T->brk = 1;
       return;
     }
     a = gk / dk;
@@ -616,8 +644,8 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
         sa = make_double2(-S.alpha_c * (double)rc_[j].x, -S.alpha_c * (double)rc_[j].y);
         acc += sa.x * sa.x + sa.y * sa.y;
       }
-      st2(sout, c, s);
-      st2(rn, c, rc_[j]);
+      st2s(sout, c, s);
+      st2s(rn, c, rc_[j]);
       acc += norm2d(s);
     }
     __syncthreads();
@@ -633,13 +661,74 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
 }
 
 // ---------------------------------------------------------------------------
-// Software-pipelined variants (same arithmetic, same outputs bit for bit):
-// while plane z is computed, the raw inputs of plane z+2 are already in
-// flight and plane z+1 waits complete in LDS, so a wavefront no longer stalls
-// on the loads it is about to use.  LDS holds three planes (z, z+1, z+2).
+// Software-pipelined variants (same arithmetic, same outputs bit for bit).
+// While plane z is computed, the raw inputs of plane z+3 are in flight and
+// plane z+2 is committed to LDS; x, m (and p_{k-2}) of plane z+1 are loaded one
+// step ahead.  LDS holds three planes (z, z+1, z+2).
+//
+// Every vector access of the z-march is an unconditional buffer instruction:
+// each workgroup builds buffer resources that cover exactly the planes of its
+// slab (plus the one-plane halo for the stencil inputs), and cells outside the
+// grid get an out-of-range offset, so reads outside the domain return zero and
+// stores there are dropped by the hardware.  Without branches around memory
+// instructions the compiler's wait counts stay exact and a wavefront waits only
+// for the plane it is about to use, not for its own prefetches.  The march is
+// unrolled by two so that the one-plane-ahead registers swap roles instead of
+// being copied (a copy of a pending load would force a wait).  Receivers are
+// located with a per-column bit mask of the slab's planes, so the per-plane
+// test touches no memory.
 // ---------------------------------------------------------------------------
 
-template <int W, int RY>
+typedef __amdgpu_buffer_rsrc_t BufRes;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kOOB = 0x80000000u;   // beyond any resource (records < 2^31)
+constexpr int kBufFlags = 0x00020000;    // raw 32-bit buffer, gfx9 family
+constexpr int kStoreNT = 2;              // non-temporal store
+
+// Resource over elements [first, first + count) of v (elem bytes each).
+__device__ __forceinline__ BufRes mkbuf(const void* v, int64_t first, int64_t count, int elem) {
+  const char* b = static_cast<const char*>(v) + first * elem;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b), (short)0, (int)(count * elem), kBufFlags);
+}
+__device__ __forceinline__ float2 bld2(BufRes r, unsigned off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float bld1(BufRes r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void bst2(BufRes r, unsigned off, float2 v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kStoreNT);
+}
+
+// Receivers of a thread's RY columns inside the slab [z0, z1): bit (z - z0) of
+// mask[j] is set where a receiver sits (at most one per cell, duplicates are
+// rejected on the host); cur[j] is its first entry.  Requires z1 - z0 <= 64.
+template <int RY>
+struct RecMask {
+  uint64_t mask[RY];
+  int cur[RY];
+  __device__ void setup(const SysDev& S, int gx, const int* gy, const bool* in, int z0, int z1) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      mask[j] = 0; cur[j] = 0;
+      if (S.colmap != nullptr && in[j]) {
+        const int2 be = ld2i(gptr(S.colmap), gy[j] * S.nx + gx);
+        int c = be.x;
+        while (c < be.y && ld2i(gptr(S.entries), c).x < z0) ++c;
+        cur[j] = c;
+        for (int e = c; e < be.y; ++e) {
+          const int ze = ld2i(gptr(S.entries), e).x;
+          if (ze >= z1) break;
+          mask[j] |= uint64_t(1) << (ze - z0);
+        }
+      }
+    }
+  }
+  __device__ bool at(int j, int dz) const { return dz < 64 && ((mask[j] >> dz) & 1); }
+  __device__ int take(const SysDev& S, int j) { return ld2i(gptr(S.entries), cur[j]++).y; }
+};
+
+template <int W, int RY, int XS>
 __global__ void __launch_bounds__(64 * W)
 k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_s,
          double* __restrict__ part_d, const GroupDesc* __restrict__ gd, int ngroups) {
@@ -667,9 +756,17 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   const double gk = block_sum_slots<W>(part_s + S.slot_base, ntiles, red);
   const double g0 = (k == 0) ? gk : T->gamma0;
   const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
-  const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
+  // brk: the adjoint launch of this same k broke down; this launch only finishes x
+  const bool brk = T->brk != 0;
+  const bool stop = brk || (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
   const double beta = (k == 0) ? 0.0 : gk / T->gamma[(k - 1) & 1];
   const double aprev = (k == 0) ? 0.0 : T->a[(k - 1) & 1];
+  // x takes the pending steps on even iterations and when the system stops:
+  // c1 p_{k-1} (+ c2 p_{k-2} at even k >= 2; a_{k-2} is still in a[k & 1]).
+  // After a breakdown this k already ran once: only an odd k left a step pending.
+  const bool xstep = brk ? (k & 1) == 1 : stop ? (k >= 1) : (k >= 2 && (k & 1) == 0);
+  const double c1 = xstep ? aprev : 0.0;
+  const double c2 = (xstep && !brk && k >= 2 && (k & 1) == 0) ? T->a[k & 1] : 0.0;
   if (tile == 0 && tid == 0) {
     T->gamma[k & 1] = gk;
     T->gmin[k & 1] = fmin(gmin, gk);
@@ -680,15 +777,11 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   Ctx C;
   C.setup(S, tile, lane, w, tiles_x, tiles_y, tz);
   const int plane = C.plane;
-  const double af = aprev, bf = beta;
+  const double bf = beta;
   const double w2 = S.omega_d * S.omega_d;
-  const GLOBAL float2* __restrict__ sv = gptr((const float2*)S.s);
-  const GLOBAL float2* __restrict__ po = gptr((const float2*)S.p[k & 1]);
-  GLOBAL float2* __restrict__ pn = gptr(S.p[(k + 1) & 1]);
-  GLOBAL float2* __restrict__ xv = gptr(S.x);
-  GLOBAL float2* __restrict__ tout = gptr(S.t);
-  GLOBAL float2* __restrict__ t2v = gptr(S.t2);
-  const GLOBAL float* __restrict__ mv = gptr(S.m);
+  int coff[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
 
   const int sxy = S.src % plane, sz = S.src / plane;
   const int sx = sxy % S.nx, sy = sxy / S.nx;
@@ -699,22 +792,28 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       if (C.gy[j] == sy) srcj = j;
   }
 
-  if (stop) {
-    if (aprev != 0.0) {
+  // x still owes the pending steps when the host's x pattern for this launch
+  // does not match this system's own (the host keeps them equal; kept correct anyway)
+  if (stop || (!XS && xstep)) {
+    if (xstep) {
+      const GLOBAL float2* __restrict__ po = gptr((const float2*)S.p[k & 1]);
+      const GLOBAL float2* __restrict__ p2v = gptr((const float2*)S.p[(k + 1) & 1]);
+      GLOBAL float2* __restrict__ xv = gptr(S.x);
       for (int z = C.z0; z < C.z1; ++z) {
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
           if (!C.in[j]) continue;
-          const int c = z * plane + C.gy[j] * S.nx + C.gx;
-          st2(xv, c, axpy2(ld2(xv, c), af, ld2(po, c)));
+          const int c = z * plane + coff[j];
+          const float2 p2 = (c2 != 0.0) ? ld2(p2v, c) : f2(0.f, 0.f);
+          st2s(xv, c, xupd2(ld2(xv, c), c2, p2, c1, ld2(po, c)));
         }
       }
-      if (srcj >= 0) {
+      if (srcj >= 0 && stop && !brk) {
         const double2 pa = T->pa;
         T->xa = make_double2(T->xa.x + aprev * pa.x, T->xa.y + aprev * pa.y);
       }
     }
-    return;
+    if (stop) return;
   }
 
   double2 pa_new = make_double2(0.0, 0.0);
@@ -724,13 +823,25 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
     T->xa = make_double2(T->xa.x + aprev * pa.x, T->xa.y + aprev * pa.y);
   }
 
-  RecCursor<RY> rc;
-  rc.setup(S, C.gx, C.gy, C.in, C.z0);
+  RecMask<RY> rc;
+  rc.setup(S, C.gx, C.gy, C.in, C.z0, C.z1);
 
   double sxy2[RY];
   const double sx2 = sponge_axis_d(C.gx, S.nx, S.nb, S.inv_nb_d);
 #pragma unroll
   for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
+
+  // buffer resources: stencil inputs over planes [zlo, zhi) (slab plus halo),
+  // the rest over the slab's own planes [z0, z1)
+  const int zlo = max(C.z0 - 1, 0), zhi = min(C.z1 + 1, S.nz);
+  const int64_t pl64 = plane;
+  const BufRes Rs = mkbuf(S.s, zlo * pl64, (zhi - zlo) * pl64, 8);
+  const BufRes Rpo = mkbuf(S.p[k & 1], zlo * pl64, (zhi - zlo) * pl64, 8);
+  const BufRes Rpn = mkbuf(S.p[(k + 1) & 1], C.z0 * pl64, (C.z1 - C.z0) * pl64, 8);
+  const BufRes Rx = mkbuf(S.x, C.z0 * pl64, (C.z1 - C.z0) * pl64, 8);
+  const BufRes Rt = mkbuf(S.t, C.z0 * pl64, (C.z1 - C.z0) * pl64, 8);
+  const BufRes Rm = mkbuf(S.m, C.z0 * pl64, (C.z1 - C.z0) * pl64, 4);
+  GLOBAL float2* __restrict__ t2v = gptr(S.t2);
 
   // halo slot geometry (fixed for the whole march)
   int hx[HS], hy[HS], hoff[HS];
@@ -746,92 +857,100 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       hoff[q] = yy * S.nx + xx;
     }
   }
-  int coff[RY];
+  // byte offset of an own cell (plane zz) in a stencil-input resource / a slab resource
+  // Byte offsets of a cell in a stencil-input resource (planes from zlo) and in
+  // a slab resource (planes from z0).  Cells outside the grid get the
+  // out-of-range bit ORed in (arithmetic, so that no branch forms around the
+  // access); planes outside a resource's range are out of range by themselves.
+  unsigned obit[RY], hbit[HS];
 #pragma unroll
-  for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
+  for (int j = 0; j < RY; ++j) obit[j] = C.in[j] ? 0u : kOOB;
+#pragma unroll
+  for (int q = 0; q < HS; ++q) hbit[q] = hin[q] ? 0u : kOOB;
+  auto hoff_b = [&](int zz, int cell, unsigned bit) -> unsigned {
+    return (unsigned)(((zz - zlo) * plane + cell) * 8) | bit;
+  };
+  auto own_b = [&](int zz, int j, int elem) -> unsigned {
+    return (unsigned)(((zz - C.z0) * plane + coff[j]) * elem) | obit[j];
+  };
 
-  // raw inputs of one plane: own rows and halo slots
-  float2 rs[RY], rp[RY], hs_[HS], hp_[HS];
+  // Raw inputs of one plane: s and p_{k-1} of the own rows and the halo, and
+  // (x-step launches) x and p_{k-2} of the own rows.  The x update of a plane
+  // is applied when the plane is committed, so every raw load is consumed right
+  // after its one wait and no loaded register lives on across planes.
+  float2 rs[RY], rp[RY], hs_[HS], hp_[HS], rx[RY], rq[RY];
   auto issue = [&](int zz) {
-    const bool ok = zz < S.nz;
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      rs[j] = f2(0.f, 0.f); rp[j] = f2(0.f, 0.f);
-      if (ok && C.in[j]) { rs[j] = ld2(sv, zz * plane + coff[j]); rp[j] = ld2(po, zz * plane + coff[j]); }
+      const unsigned o = hoff_b(zz, coff[j], obit[j]);
+      rs[j] = bld2(Rs, o);
+      rp[j] = bld2(Rpo, o);
+      if constexpr (XS != 0) {
+        const unsigned o8 = own_b(zz, j, 8);
+        rx[j] = bld2(Rx, o8);
+        rq[j] = bld2(Rpn, o8);
+      }
     }
 #pragma unroll
     for (int q = 0; q < HS; ++q) {
-      hs_[q] = f2(0.f, 0.f); hp_[q] = f2(0.f, 0.f);
-      if (ok && hin[q]) { hs_[q] = ld2(sv, zz * plane + hoff[q]); hp_[q] = ld2(po, zz * plane + hoff[q]); }
+      const unsigned o = hoff_b(zz, hoff[q], hbit[q]);
+      hs_[q] = bld2(Rs, o);
+      hp_[q] = bld2(Rpo, o);
     }
   };
-  // p_k = s + beta p_{k-1} of the issued plane into LDS buffer b and registers
-  float2 pnew[RY], pold[RY];
-  auto commit = [&](int b) {
+  // p_k = s + beta p_{k-1} of plane zz into LDS buffer b and pnew; x of plane zz
+  // (planes outside the slab are out of range of Rx: the store is dropped)
+  float2 pnew[RY];
+  auto commit = [&](int b, int zz) {
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      pold[j] = rp[j];
       pnew[j] = axpy2(rs[j], bf, rp[j]);
       pl[b][1 + w * RY + j][1 + lane] = pnew[j];
+      if constexpr (XS != 0)
+        bst2(Rx, own_b(zz, j, 8), xstep ? xupd2(rx[j], c2, rq[j], c1, rp[j]) : rx[j]);
     }
 #pragma unroll
     for (int q = 0; q < HS; ++q)
       if (tid + q * NT < Ctx::NH) pl[b][hy[q]][hx[q]] = axpy2(hs_[q], bf, hp_[q]);
   };
 
-  float2 pm[RY], pc[RY], pnx[RY], poc[RY], pon[RY];
-  // plane z0-1 (own rows only)
+  // m of the current / next plane.  Plane z0's m is loaded first: the loop's
+  // wait for it then counts every later load of the prologue, and the count the
+  // compiler derives for the loop header is the loop's own, not a drain.
+  float mA[RY], mB[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) mA[j] = bld1(Rm, own_b(C.z0, j, 4));
+  float2 pm[RY], pc[RY], pnx[RY];
+  // plane z0-1 (own rows only; zero below the grid)
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
-    pm[j] = f2(0.f, 0.f);
-    if (C.in[j] && C.z0 > 0) {
-      const int c = (C.z0 - 1) * plane + coff[j];
-      pm[j] = axpy2(ld2(sv, c), bf, ld2(po, c));
-    }
+    const unsigned o = hoff_b(C.z0 - 1, coff[j], obit[j]);
+    pm[j] = axpy2(bld2(Rs, o), bf, bld2(Rpo, o));
   }
   issue(C.z0);
-  commit(0);
+  commit(0, C.z0);
 #pragma unroll
-  for (int j = 0; j < RY; ++j) { pc[j] = pnew[j]; poc[j] = pold[j]; }
+  for (int j = 0; j < RY; ++j) pc[j] = pnew[j];
   issue(C.z0 + 1);
-  commit(1);
+  commit(1, C.z0 + 1);
 #pragma unroll
-  for (int j = 0; j < RY; ++j) { pnx[j] = pnew[j]; pon[j] = pold[j]; }
+  for (int j = 0; j < RY; ++j) pnx[j] = pnew[j];
   issue(C.z0 + 2);
-  float2 xz[RY];
-  float mz[RY];
-#pragma unroll
-  for (int j = 0; j < RY; ++j) {
-    xz[j] = f2(0.f, 0.f); mz[j] = 0.f;
-    if (C.in[j]) {
-      if (aprev != 0.0) xz[j] = ld2(xv, C.z0 * plane + coff[j]);
-      mz[j] = mv[C.z0 * plane + coff[j]];
-    }
-  }
   __syncthreads();
 
   double acc = 0.0;
   int cur = 0;
-  for (int z = C.z0; z < C.z1; ++z) {
-    const int b2 = (cur + 2) % 3;
-    // x and m of plane z+1 (used next step)
-    float2 xz1[RY];
-    float mz1[RY];
+  // one plane: uses m of plane z (mz) and loads that of plane z+1 into mn.  A
+  // step with z >= z1 (odd slab length) computes nothing that is stored or summed.
+  auto step = [&](int z, float (&mz)[RY], float (&mn)[RY]) {
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      xz1[j] = f2(0.f, 0.f); mz1[j] = 0.f;
-      if (C.in[j] && z + 1 < C.z1) {
-        if (aprev != 0.0) xz1[j] = ld2(xv, (z + 1) * plane + coff[j]);
-        mz1[j] = mv[(z + 1) * plane + coff[j]];
-      }
-    }
-    // t = S p at plane z
+    for (int j = 0; j < RY; ++j) mn[j] = bld1(Rm, own_b(z + 1, j, 4));
+    const bool zin = z < C.z1;
+    const unsigned zbit = zin ? 0u : kOOB;
     const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      if (!C.in[j]) continue;
       const int ly = w * RY + j;
-      const int c = z * plane + coff[j];
       const float2 xm = pl[cur][ly + 1][lane];
       const float2 xp = pl[cur][ly + 1][lane + 2];
       const float2 ym = (j > 0) ? pc[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
@@ -843,11 +962,12 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
         td.y -= S.alpha_c * pa_new.y;
       }
       const float2 tv = round2(td);
-      st2(tout, c, tv);
-      st2(pn, c, pc[j]);
-      if (aprev != 0.0) st2(xv, c, axpy2(xz[j], af, poc[j]));
-      acc += norm2d(tv);
-      while (rc.nz_[j] == z) {
+      const bool live = C.in[j] && zin;
+      const unsigned o8 = own_b(z, j, 8) | zbit;
+      bst2(Rt, o8, tv);
+      bst2(Rpn, o8, pc[j]);
+      acc += live ? norm2d(tv) : 0.0;
+      if (rc.at(j, z - C.z0)) {  // receiver row of S p: lambda p at the receiver cell
         const int q = rc.take(S, j);
         const float2 tq = f2((float)(S.lam_d * pc[j].x), (float)(S.lam_d * pc[j].y));
         st2(t2v, q, tq);
@@ -855,19 +975,22 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       }
     }
     // plane z+2 (its loads were issued one step ago) into LDS; then prefetch z+3
-    commit(b2);
-    float2 pn2[RY], pon2[RY];
+    commit((cur + 2) % 3, z + 2);
+    float2 pn2[RY];
 #pragma unroll
-    for (int j = 0; j < RY; ++j) { pn2[j] = pnew[j]; pon2[j] = pold[j]; }
-    if (z + 3 <= C.z1) issue(z + 3);
+    for (int j = 0; j < RY; ++j) pn2[j] = pnew[j];
+    // keep the next plane's loads below the commit: hoisted above it, they would
+    // need registers of their own and a copy (a wait) at the loop back-edge
+    __builtin_amdgcn_sched_barrier(0);
+    issue(z + 3);
     __syncthreads();
     cur = (cur + 1) % 3;
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      pm[j] = pc[j]; pc[j] = pnx[j]; pnx[j] = pn2[j];
-      poc[j] = pon[j]; pon[j] = pon2[j];
-      xz[j] = xz1[j]; mz[j] = mz1[j];
-    }
+    for (int j = 0; j < RY; ++j) { pm[j] = pc[j]; pc[j] = pnx[j]; pnx[j] = pn2[j]; }
+  };
+  for (int z = C.z0; z < C.z1; z += 2) {
+    step(z, mA, mB);
+    step(z + 1, mB, mA);
   }
 
   const double tot = block_reduce<W>(acc, red);
@@ -907,10 +1030,12 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
     const double gk = T->gamma[k & 1];
     const double g0 = T->gamma0;
     const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
-    const bool stop = (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
+    const bool brk = T->brk != 0;
+    const bool stop = brk || (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
     if (stop) {
       if (tile == 0 && tid == 0) {
-        T->status = (g0 == 0.0) ? kZeroRhs
+        T->status = brk ? kBreakdown
+                  : (g0 == 0.0) ? kZeroRhs
                   : (gk <= S.rtol2 * g0) ? kConverged
                   : (gk > kDivergeRatio * gmin) ? kDiverged : kMaxIter;
         T->iters = k;
@@ -919,10 +1044,9 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
     }
     const double dk = block_sum_slots<W>(part_d + S.slot_base, ntiles, red);
     if (!(dk > 0.0) || !(dk <= DBL_MAX) || !(gk <= DBL_MAX)) {
-      if (tile == 0 && tid == 0) {
-        T->status = kBreakdown;
-        T->iters = k;
-      }
+      // x may still lack a step: the next forward launch (same k) finishes it
+      // and the adjoint launch after it records the status
+      if (tile == 0 && tid == 0) T->brk = 1;
       return;
     }
     a = gk / dk;
@@ -934,13 +1058,9 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   const int plane = C.plane;
   const double af = a;
   const double w2 = S.omega_d * S.omega_d;
-  const GLOBAL float2* __restrict__ ro = gptr((const float2*)S.r[setup ? 1 : (k & 1)]);
-  GLOBAL float2* __restrict__ rn = gptr(S.r[setup ? 0 : ((k + 1) & 1)]);
-  const GLOBAL float2* __restrict__ tv = gptr((const float2*)S.t);
-  GLOBAL float2* __restrict__ sout = gptr(S.s);
-  GLOBAL float2* __restrict__ r2v = gptr(S.r2);
-  const GLOBAL float2* __restrict__ t2v = gptr((const float2*)S.t2);
-  const GLOBAL float* __restrict__ mv = gptr(S.m);
+  int coff[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
 
   const int sxy = S.src % plane, sz = S.src / plane;
   const int sx = sxy % S.nx, sy = sxy / S.nx;
@@ -951,13 +1071,23 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       if (C.gy[j] == sy) srcj = j;
   }
 
-  RecCursor<RY> rc;
-  rc.setup(S, C.gx, C.gy, C.in, C.z0);
+  RecMask<RY> rc;
+  rc.setup(S, C.gx, C.gy, C.in, C.z0, C.z1);
 
   double sxy2[RY];
   const double sx2 = sponge_axis_d(C.gx, S.nx, S.nb, S.inv_nb_d);
 #pragma unroll
   for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
+
+  const int zlo = max(C.z0 - 1, 0), zhi = min(C.z1 + 1, S.nz);
+  const int64_t pl64 = plane;
+  const BufRes Rro = mkbuf(S.r[setup ? 1 : (k & 1)], zlo * pl64, (zhi - zlo) * pl64, 8);
+  const BufRes Rt = mkbuf(S.t, zlo * pl64, (zhi - zlo) * pl64, 8);
+  const BufRes Rrn = mkbuf(S.r[setup ? 0 : ((k + 1) & 1)], C.z0 * pl64, (C.z1 - C.z0) * pl64, 8);
+  const BufRes Rso = mkbuf(S.s, C.z0 * pl64, (C.z1 - C.z0) * pl64, 8);
+  const BufRes Rm = mkbuf(S.m, C.z0 * pl64, (C.z1 - C.z0) * pl64, 4);
+  GLOBAL float2* __restrict__ r2v = gptr(S.r2);
+  const GLOBAL float2* __restrict__ t2v = gptr((const float2*)S.t2);
 
   int hx[HS], hy[HS], hoff[HS];
   bool hin[HS];
@@ -972,28 +1102,37 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       hoff[q] = yy * S.nx + xx;
     }
   }
-  int coff[RY];
+  // Byte offsets of a cell in a stencil-input resource (planes from zlo) and in
+  // a slab resource (planes from z0).  Cells outside the grid get the
+  // out-of-range bit ORed in (arithmetic, so that no branch forms around the
+  // access); planes outside a resource's range are out of range by themselves.
+  unsigned obit[RY], hbit[HS];
 #pragma unroll
-  for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
+  for (int j = 0; j < RY; ++j) obit[j] = C.in[j] ? 0u : kOOB;
+#pragma unroll
+  for (int q = 0; q < HS; ++q) hbit[q] = hin[q] ? 0u : kOOB;
+  auto hoff_b = [&](int zz, int cell, unsigned bit) -> unsigned {
+    return (unsigned)(((zz - zlo) * plane + cell) * 8) | bit;
+  };
+  auto own_b = [&](int zz, int j, int elem) -> unsigned {
+    return (unsigned)(((zz - C.z0) * plane + coff[j]) * elem) | obit[j];
+  };
+  // the set-up pass (s_0 = S^H b) reads no t
+  const unsigned tbit = setup ? kOOB : 0u;
 
   float2 rr[RY], rt[RY], hr[HS], ht[HS];
   auto issue = [&](int zz) {
-    const bool ok = zz < S.nz;
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      rr[j] = f2(0.f, 0.f); rt[j] = f2(0.f, 0.f);
-      if (ok && C.in[j]) {
-        rr[j] = ld2(ro, zz * plane + coff[j]);
-        if (!setup) rt[j] = ld2(tv, zz * plane + coff[j]);
-      }
+      const unsigned o = hoff_b(zz, coff[j], obit[j]);
+      rr[j] = bld2(Rro, o);
+      rt[j] = bld2(Rt, o | tbit);
     }
 #pragma unroll
     for (int q = 0; q < HS; ++q) {
-      hr[q] = f2(0.f, 0.f); ht[q] = f2(0.f, 0.f);
-      if (ok && hin[q]) {
-        hr[q] = ld2(ro, zz * plane + hoff[q]);
-        if (!setup) ht[q] = ld2(tv, zz * plane + hoff[q]);
-      }
+      const unsigned o = hoff_b(zz, hoff[q], hbit[q]);
+      hr[q] = bld2(Rro, o);
+      ht[q] = bld2(Rt, o | tbit);
     }
   };
   float2 rnew[RY];
@@ -1008,15 +1147,17 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       if (tid + q * NT < Ctx::NH) pl[b][hy[q]][hx[q]] = setup ? hr[q] : axpy2(hr[q], -af, ht[q]);
   };
 
+  // m of plane z0 first (see the forward kernel)
+  float mA[RY], mB[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) mA[j] = bld1(Rm, own_b(C.z0, j, 4));
   float2 rm[RY], rc_[RY], rnx[RY];
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
-    rm[j] = f2(0.f, 0.f);
-    if (C.in[j] && C.z0 > 0) {
-      const int c = (C.z0 - 1) * plane + coff[j];
-      const float2 r0 = ld2(ro, c);
-      rm[j] = setup ? r0 : axpy2(r0, -af, ld2(tv, c));
-    }
+    const unsigned o = hoff_b(C.z0 - 1, coff[j], obit[j]);
+    const float2 r0 = bld2(Rro, o);
+    const float2 t0 = bld2(Rt, o | tbit);
+    rm[j] = setup ? r0 : axpy2(r0, -af, t0);
   }
   issue(C.z0);
   commit(0);
@@ -1027,32 +1168,27 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 #pragma unroll
   for (int j = 0; j < RY; ++j) rnx[j] = rnew[j];
   issue(C.z0 + 2);
-  float mz[RY];
-#pragma unroll
-  for (int j = 0; j < RY; ++j) mz[j] = C.in[j] ? mv[C.z0 * plane + coff[j]] : 0.f;
   __syncthreads();
 
   double acc = 0.0;
   double2 sa = make_double2(0.0, 0.0);
   int cur = 0;
-  for (int z = C.z0; z < C.z1; ++z) {
-    const int b2 = (cur + 2) % 3;
-    float mz1[RY];
+  auto step = [&](int z, float (&mz)[RY], float (&mn)[RY]) {
 #pragma unroll
-    for (int j = 0; j < RY; ++j) mz1[j] = (C.in[j] && z + 1 < C.z1) ? mv[(z + 1) * plane + coff[j]] : 0.f;
+    for (int j = 0; j < RY; ++j) mn[j] = bld1(Rm, own_b(z + 1, j, 4));
+    const bool zin = z < C.z1;
+    const unsigned zbit = zin ? 0u : kOOB;
     const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      if (!C.in[j]) continue;
       const int ly = w * RY + j;
-      const int c = z * plane + coff[j];
       const float2 xm = pl[cur][ly + 1][lane];
       const float2 xp = pl[cur][ly + 1][lane + 2];
       const float2 ym = (j > 0) ? rc_[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
       const float2 yp = (j < RY - 1) ? rc_[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
       const double b = S.sp_scale_d * (sxy2[j] + sz2);
       double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], S.h2inv_d, w2 * (double)mz[j], S.omega_d * b);
-      while (rc.nz_[j] == z) {
+      if (rc.at(j, z - C.z0)) {  // receiver column of S^H: lambda r2 at the receiver cell
         const int q = rc.take(S, j);
         float2 r2 = ld2(r2v, q);
         if (!setup) {
@@ -1067,19 +1203,26 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
         sa = make_double2(-S.alpha_c * (double)rc_[j].x, -S.alpha_c * (double)rc_[j].y);
         acc += sa.x * sa.x + sa.y * sa.y;
       }
-      st2(sout, c, s);
-      st2(rn, c, rc_[j]);
-      acc += norm2d(s);
+      const bool live = C.in[j] && zin;
+      const unsigned o8 = own_b(z, j, 8) | zbit;
+      bst2(Rso, o8, s);
+      bst2(Rrn, o8, rc_[j]);
+      acc += live ? norm2d(s) : 0.0;
     }
-    commit(b2);
+    commit((cur + 2) % 3);
     float2 rn2[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) rn2[j] = rnew[j];
-    if (z + 3 <= C.z1) issue(z + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    issue(z + 3);
     __syncthreads();
     cur = (cur + 1) % 3;
 #pragma unroll
-    for (int j = 0; j < RY; ++j) { rm[j] = rc_[j]; rc_[j] = rnx[j]; rnx[j] = rn2[j]; mz[j] = mz1[j]; }
+    for (int j = 0; j < RY; ++j) { rm[j] = rc_[j]; rc_[j] = rnx[j]; rnx[j] = rn2[j]; }
+  };
+  for (int z = C.z0; z < C.z1; z += 2) {
+    step(z, mA, mB);
+    step(z + 1, mB, mA);
   }
 
   const double tot = block_reduce<W>(acc, red);
@@ -1095,20 +1238,23 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 #define WRI_TILE_LIST(X) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(2, 8)
 
 bool cfg_supported(const TileCfg& c) {
-#define X(W_, R_) if (c.w == W_ && c.ry == R_) return c.tz >= 1 && (c.pf == 0 || c.pf == 1);
+#define X(W_, R_) if (c.w == W_ && c.ry == R_) return c.tz >= 1 && c.tz <= 64 && (c.pf == 0 || c.pf == 1);
   WRI_TILE_LIST(X)
 #undef X
   return false;
 }
 
 hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_s, double* part_d,
-                      const GroupDesc* gd, int ngroups, int nblocks, hipStream_t s) {
+                      const GroupDesc* gd, int ngroups, int nblocks, int k, hipStream_t s) {
   if (nblocks <= 0 || ngroups <= 0) return hipSuccess;
   const unsigned nb = (unsigned)nblocks;
 #define X(W_, R_)                                                                                   \
   if (c.w == W_ && c.ry == R_) {                                                                    \
-    if (c.pf)                                                                                       \
-      hipLaunchKernelGGL((k_fwd_pf<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d,  \
+    if (c.pf && fwd_x_step(k))                                                                      \
+      hipLaunchKernelGGL((k_fwd_pf<W_, R_, 1>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d, \
+                         gd, ngroups);                                                              \
+    else if (c.pf)                                                                                  \
+      hipLaunchKernelGGL((k_fwd_pf<W_, R_, 0>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d, \
                          gd, ngroups);                                                              \
     else                                                                                            \
       hipLaunchKernelGGL((k_fwd<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d,     \

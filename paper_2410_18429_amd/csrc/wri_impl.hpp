@@ -67,7 +67,9 @@ struct SysState {
   int iterB;          // iteration index read by the adjoint kernel
   int status;         // kActive or final
   int iters;
-  int pad_[4];
+  int brk;            // set by the adjoint kernel on a breakdown; the next pair of
+                      // launches finishes x and records the status
+  int pad_[3];
 };
 
 struct TileCfg {
@@ -94,8 +96,12 @@ struct GroupDesc {
 // ---- launchers (kernels.hip) -------------------------------------------
 hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s);
 // Fused CGLS launches over all groups (same tile shape c for all of them).
+// k: the iteration every active system of the launch is at (systems of one
+// call iterate in lockstep); selects the variant of the forward kernel that
+// updates x (even k >= 2) or leaves it alone (odd k, k = 0).
+inline bool fwd_x_step(int64_t k) { return k >= 2 && (k & 1) == 0; }
 hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_s, double* part_d,
-                      const GroupDesc* gd, int ngroups, int nblocks, hipStream_t s);
+                      const GroupDesc* gd, int ngroups, int nblocks, int k, hipStream_t s);
 hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_d, double* part_s,
                       const GroupDesc* gd, int ngroups, int nblocks, hipStream_t s, int setup_only = 0);
 hipError_t launch_grad(const SysDev* sys, SysState* st, int rhs0, int nrhs, int n, float* grad,

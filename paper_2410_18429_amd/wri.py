@@ -64,9 +64,10 @@ class WriResult(ctypes.Structure):
 
 class WriTiming(ctypes.Structure):
     _fields_ = [("fwd_ms", c_double), ("adj_ms", c_double), ("fwd_launches", ctypes.c_int64),
-                ("adj_launches", ctypes.c_int64), ("cell_iters", ctypes.c_int64), ("fwd_ms_full", c_double),
-                ("adj_ms_full", c_double), ("fwd_launches_full", ctypes.c_int64),
-                ("adj_launches_full", ctypes.c_int64), ("cells_per_launch_full", ctypes.c_int64)]
+                ("adj_launches", ctypes.c_int64), ("fwd_bytes", c_double), ("adj_bytes", c_double),
+                ("fwd_ms_full", c_double), ("adj_ms_full", c_double), ("fwd_launches_full", ctypes.c_int64),
+                ("adj_launches_full", ctypes.c_int64), ("fwd_bytes_full", c_double),
+                ("adj_bytes_full", c_double)]
 
 
 class WriError(RuntimeError):

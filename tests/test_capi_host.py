@@ -46,7 +46,7 @@ def test_struct_layout_matches_header():
       printf("%zu %zu %zu %zu\n", offsetof(wri_result, relres), offsetof(wri_result, J),
              offsetof(wri_result, alpha), offsetof(wri_result, alpha_ls));
       printf("%zu %zu %zu\n", sizeof(wri_timing), offsetof(wri_timing, fwd_ms_full),
-             offsetof(wri_timing, cells_per_launch_full));
+             offsetof(wri_timing, adj_bytes_full));
       return 0;
     }
     """
@@ -63,7 +63,7 @@ def test_struct_layout_matches_header():
                           S.rec.offset, S.d.offset, G.h.offset]
     assert vals[11:15] == [R.relres.offset, R.J.offset, R.alpha.offset, R.alpha_ls.offset]
     Tm = wri.WriTiming
-    assert vals[15:] == [ctypes.sizeof(Tm), Tm.fwd_ms_full.offset, Tm.cells_per_launch_full.offset]
+    assert vals[15:] == [ctypes.sizeof(Tm), Tm.fwd_ms_full.offset, Tm.adj_bytes_full.offset]
 
 
 def _mk(n_rec=4, dup=False, src=5, rec_bad=False, grid=0, lam=0.1, omega=30.0, rtol=1e-6, nb=2, v_ref=1500.0):
@@ -109,6 +109,11 @@ def test_validate_mode_and_iters():
     assert L.wri_validate(bad, 1, s, 1, wri.KNOWN, 1) == wri.EINVAL
     huge = (wri.WriGrid * 1)(wri.WriGrid(2048, 2048, 512, 0, 10.0, 1500.0))
     assert L.wri_validate(huge, 1, None, 0, wri.KNOWN, 1) == wri.EINVAL
+    wide = (wri.WriGrid * 1)(wri.WriGrid(2000, 2000, 10, 0, 10.0, 1500.0))   # 4e6 cells in one plane
+    assert L.wri_validate(wide, 1, None, 0, wri.KNOWN, 1) == wri.EINVAL
+    assert "plane" in wri.last_error()
+    ok = (wri.WriGrid * 1)(wri.WriGrid(1958, 1958, 10, 0, 10.0, 1500.0))
+    assert L.wri_validate(ok, 1, None, 0, wri.KNOWN, 1) == wri.OK
 
 
 def test_workspace_bytes_and_dedup():

@@ -75,7 +75,7 @@ def test_apply_helmholtz_matches_oracle(shape, adjoint):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mode", ["estimate", "known"])
-@pytest.mark.parametrize("k", [1, 2, 7])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 7])
 def test_fused_iterates_match_reference_cgls(mode, k):
     _say(f"iterates mode={mode} k={k}")
     p = wri_synth.custom_problem((70, 37, 19), nb=3, n_src=2, n_rec=12, seed=21, freqs=(7.0,), rtol=0.0)
@@ -105,7 +105,8 @@ SHAPES = [(16, 16, 16), (70, 37, 19), (33, 65, 12), (5, 6, 7)]
 def test_solve_parity_exact(shape, mode):
     _say(f"solve shape={shape} mode={mode}")
     # sponge of up to 6 cells: the weakly damped 3-cell sponge on 70x37x19 leaves a KNOWN-mode
-    # system whose float32 attainable accuracy is ~2e-4 (see the precision section of the design doc)
+    # system whose float32 attainable accuracy is ~2e-4 (float32 storage of the LS residual
+    # bounds CGLS at about eps * cond(S)^2 * |r*| relative to |S| |x|)
     p = wri_synth.custom_problem(shape, nb=min(6, min(shape) // 3), n_src=2, n_rec=10, seed=7,
                                  freqs=(6.0, 9.0), rtol=PARITY_RTOL)
     ref = oracle.objective_grad(p, mode=mode)
@@ -218,14 +219,18 @@ def test_uneven_grids_adaptive_tolerances():
         assert res[i]["status"] == "converged" and res[i]["relres"] <= s.rtol
         assert abs(res[i]["iters"] - ref["iters"]) <= max(2, 0.1 * ref["iters"]), (res[i]["iters"], ref["iters"])
         # float64 true normal residual of the GPU iterate, against the floor set
-        # by storing the exact minimiser in complex64 (the iteration's own
-        # rounding typically lands within a few times that floor)
+        # by storing the exact minimiser in complex64.  CGLS with complex64
+        # vectors levels off at a multiple of that floor that grows with the
+        # conditioning of S (the recurred residual keeps falling, the true one
+        # does not): on these systems a float32-storage CGLS run on the CPU
+        # with the same updates lands at 3x (system 1) to 22x (system 5) the
+        # floor, so tolerances below the floor are met in the recurred sense only.
         tr = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d, _np(u[i]), res[i]["alpha"])
         ue, ae = oracle.solve_estimate(A, P, s.lam, s.src, s.d)
         floor = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d,
                                        ue.astype(np.complex64).astype(np.complex128), ae)
         _say(f"  sys {i}: rtol {s.rtol:.1e} true normal residual {tr:.2e} (c64 floor {floor:.2e})")
-        assert tr <= max(2 * s.rtol, 10 * floor), (tr, s.rtol, floor)
+        assert tr <= max(2 * s.rtol, 50 * floor), (tr, s.rtol, floor)
 
 
 # --------------------------------------------------------------------------
