@@ -434,6 +434,11 @@ int set_config(Ctx& C, const TileCfg& cfg) {
     b0 += d.nrhs * d.ntiles;
   }
   C.nblocks = b0;
+  // XCD chunk: an eighth of the largest system's tiles (each XCD then holds a
+  // share of every system), at least 1 and at most 32 tiles
+  int tmax = 1;
+  for (const auto& d : C.hgd) tmax = std::max(tmax, d.ntiles);
+  for (auto& d : C.hgd) d.xchunk = std::max(1, std::min(32, tmax / kXCD));
   if (!C.hgd.empty()) {
     WRI_HIP(hipMemcpyAsync(C.dgd, C.hgd.data(), sizeof(GroupDesc) * C.hgd.size(), hipMemcpyHostToDevice, C.st));
     WRI_HIP(hipStreamSynchronize(C.st));  // C.hgd may change before an asynchronous copy would finish

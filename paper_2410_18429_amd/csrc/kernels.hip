@@ -65,12 +65,18 @@ __device__ __forceinline__ int2 ld2i(const GLOBAL int2* p, int i) {
   return __builtin_bit_cast(int2, *((const GLOBAL unsigned long long*)p + i));
 }
 
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  // Blocks go round-robin to the XCDs; give each XCD a contiguous range of
-  // logical tiles so that halo re-reads of neighbouring tiles hit its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb, int q) {
+  // Blocks go round-robin to the XCDs (b % 8).  The logical sequence of
+  // (group, system, tile) is cut into chunks of q consecutive tiles, dealt to the
+  // XCDs round-robin as well: the tiles of a chunk are spatial neighbours on
+  // one XCD (halo re-reads hit its L2), and every XCD holds a share of every
+  // system, so no XCD idles while others still work when some systems of the
+  // batch have converged.  Blocks past the last complete round keep their index.
   const int xcd = b % kXCD, local = b / kXCD;
-  const int per = nb / kXCD, rem = nb % kXCD;
-  return xcd * per + min(xcd, rem) + local;
+  const int full = nb / (kXCD * q) * (kXCD * q);
+  if (b >= full) return b;
+  const int round = local / q, off = local - round * q;
+  return (round * kXCD + xcd) * q + off;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -287,7 +293,7 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   __shared__ double red[W + 1];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int logical = xcd_remap(blockIdx.x, gridDim.x, gd[0].xchunk);
   int g = 0;
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
@@ -493,7 +499,7 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   __shared__ double red[W + 1];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int logical = xcd_remap(blockIdx.x, gridDim.x, gd[0].xchunk);
   int g = 0;
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
@@ -739,7 +745,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   __shared__ double red[W + 1];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int logical = xcd_remap(blockIdx.x, gridDim.x, gd[0].xchunk);
   int g = 0;
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
@@ -1009,7 +1015,7 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   __shared__ double red[W + 1];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int logical = xcd_remap(blockIdx.x, gridDim.x, gd[0].xchunk);
   int g = 0;
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;

@@ -91,6 +91,7 @@ struct GroupDesc {
   int block0;
   int tile_major;  // 1: consecutive blocks take the same tile of successive systems
                    //    (the tile of m is then read once per XCD for the whole group)
+  int xchunk;      // tiles per XCD chunk (same value in every entry of a table)
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
