@@ -38,15 +38,33 @@ BYTES_NOTE = {"fwd": "36, +24 on even iterations (x update of two steps)", "adj"
 
 # HBM traffic of one full-batch launch (48 systems x 128^3) from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, median over the launches of a 20-iteration
-# probe), each scaled by what the counter reads for a 1 GiB device copy (FETCH_SIZE x 2.000,
-# WRITE_SIZE x 1.000).  Valid only for the kernel source it was measured on (sha256 prefix);
+# probe with the tile forced), each scaled by what the counter reads for a 1 GiB device copy
+# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  "fwd_x" is the forward launch that also updates x
+# (even iterations).  Valid only for the solver sources it was measured on (sha256 prefix of
+# kernels.hip + capi.hip + wri_impl.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "kernels_sha256": "46f2a7555a7e72e1",
-    "fwd": {"fetch_kib": 1652400.8, "write_kib": 2359752.5},
-    "adj": {"fetch_kib": 1110978.2, "write_kib": 1573217.3},
+    "sources_sha256": "bbc4a5dcd39b66ae",
+    "tiles": {
+        "8,1,32,1,0": {"fwd_x": {"fetch_kib": 1954908.2, "write_kib": 2359507.2},
+                       "fwd": {"fetch_kib": 1110185.6, "write_kib": 1573024.5},
+                       "adj": {"fetch_kib": 1120698.1, "write_kib": 1573063.1}},
+        "4,2,32,1,0": {"fwd_x": {"fetch_kib": 2043901.1, "write_kib": 2359650.0},
+                       "fwd": {"fetch_kib": 1181281.7, "write_kib": 1573106.2},
+                       "adj": {"fetch_kib": 1153011.4, "write_kib": 1573160.2}},
+    },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
+
+
+def _sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "capi.hip", "wri_impl.hpp"):
+        with open(os.path.join(ROOT, "paper_2410_18429_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 
 def _cpu_worker(args):
@@ -167,13 +185,13 @@ def main():
     dominant = "fwd" if kt["fwd_ms"] >= kt["adj_ms"] else "adj"
     ach = fwd_gbs if dominant == "fwd" else adj_gbs
     ach_full = fwd_full_gbs if dominant == "fwd" else adj_full_gbs
+    tile = f"{kt['tile_w']},{kt['tile_ry']},{kt['tile_tz']},{kt['tile_pf']},{kt['tile_order']}"
     traffic = None
-    with open(os.path.join(ROOT, "paper_2410_18429_amd", "csrc", "kernels.hip"), "rb") as f:
-        import hashlib
-        same_kernels = hashlib.sha256(f.read()).hexdigest()[:16] == TRAFFIC["kernels_sha256"]
-    if same_kernels and args.config == "differentiation":
-        tr = TRAFFIC[dominant]
-        traffic = round(1024.0 * (tr["fetch_kib"] * TRAFFIC["fetch_scale"] + tr["write_kib"] * TRAFFIC["write_scale"]))
+    tt = TRAFFIC["tiles"].get(tile)
+    if tt is not None and args.config == "differentiation" and _sources_sha() == TRAFFIC["sources_sha256"]:
+        per = lambda v: 1024.0 * (v["fetch_kib"] * TRAFFIC["fetch_scale"] + v["write_kib"] * TRAFFIC["write_scale"])
+        # the forward launches alternate between the x-updating and the plain variant
+        traffic = round(0.5 * (per(tt["fwd_x"]) + per(tt["fwd"]))) if dominant == "fwd" else round(per(tt["adj"]))
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per full-batch launch",
@@ -187,7 +205,7 @@ def main():
                 "avg_launch_ms_full_batch": round(fwd_full_ms if dominant == "fwd" else adj_full_ms, 4),
                 "fwd_gbs": round(fwd_gbs, 1), "adj_gbs": round(adj_gbs, 1),
                 "fwd_gbs_full_batch": round(fwd_full_gbs, 1), "adj_gbs_full_batch": round(adj_full_gbs, 1),
-                "bytes_per_cell": BYTES_NOTE}
+                "bytes_per_cell": BYTES_NOTE, "tile": tile}
 
     plain = None
     if not args.no_plain and args.plain_sample > 0:

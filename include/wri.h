@@ -210,6 +210,10 @@ typedef struct {
                                             still iterating (whole batch resident)       */
   int64_t fwd_launches_full, adj_launches_full;
   double  fwd_bytes_full, adj_bytes_full;
+  int32_t tile_w, tile_ry, tile_tz, tile_pf, tile_order; /* tile shape of the fused launches
+                                                           (waves, rows per wave, z-slab,
+                                                           pipelined, tile-major order)  */
+  int32_t reserved_;
 } wri_timing;
 
 /* Fills *out; WRI_EINVAL if no timed call has completed on this thread. */

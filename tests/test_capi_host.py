@@ -45,8 +45,8 @@ def test_struct_layout_matches_header():
              offsetof(wri_system, rec), offsetof(wri_system, d), offsetof(wri_grid, h));
       printf("%zu %zu %zu %zu\n", offsetof(wri_result, relres), offsetof(wri_result, J),
              offsetof(wri_result, alpha), offsetof(wri_result, alpha_ls));
-      printf("%zu %zu %zu\n", sizeof(wri_timing), offsetof(wri_timing, fwd_ms_full),
-             offsetof(wri_timing, adj_bytes_full));
+      printf("%zu %zu %zu %zu\n", sizeof(wri_timing), offsetof(wri_timing, fwd_ms_full),
+             offsetof(wri_timing, adj_bytes_full), offsetof(wri_timing, tile_order));
       return 0;
     }
     """
@@ -63,7 +63,7 @@ def test_struct_layout_matches_header():
                           S.rec.offset, S.d.offset, G.h.offset]
     assert vals[11:15] == [R.relres.offset, R.J.offset, R.alpha.offset, R.alpha_ls.offset]
     Tm = wri.WriTiming
-    assert vals[15:] == [ctypes.sizeof(Tm), Tm.fwd_ms_full.offset, Tm.adj_bytes_full.offset]
+    assert vals[15:] == [ctypes.sizeof(Tm), Tm.fwd_ms_full.offset, Tm.adj_bytes_full.offset, Tm.tile_order.offset]
 
 
 def _mk(n_rec=4, dup=False, src=5, rec_bad=False, grid=0, lam=0.1, omega=30.0, rtol=1e-6, nb=2, v_ref=1500.0):
