@@ -87,6 +87,63 @@ def helmholtz(grid, m: np.ndarray, omega: float, b: Optional[np.ndarray] = None)
     return (laplacian(grid).astype(np.complex128) + sp.diags(diag)).tocsr()
 
 
+def helmholtz_apply(grid, m: np.ndarray, omega: float, u: np.ndarray, b: Optional[np.ndarray] = None,
+                    adjoint: bool = False) -> np.ndarray:
+    """A u (or A^H u) in complex128 without forming A, for full-size checks.
+
+    Same operator as `helmholtz`: the sum over the three axes of the second
+    difference (u[i-1] - 2 u[i] + u[i+1]) / h^2 with zero ghost values, plus
+    (omega^2 m - i omega b) u; the adjoint conjugates the diagonal (the
+    Laplacian is real symmetric)."""
+    if b is None:
+        b = sponge(grid)
+    v = np.asarray(u, dtype=np.complex128).reshape(grid.shape)
+    out = np.zeros_like(v)
+    for ax in range(3):
+        d = -2.0 * v
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(0, -1)
+        hi[ax] = slice(1, None)
+        d[tuple(lo)] += v[tuple(hi)]     # u[i+1]
+        d[tuple(hi)] += v[tuple(lo)]     # u[i-1]
+        out += d
+    out /= grid.h ** 2
+    sgn = 1.0 if adjoint else -1.0
+    diag = omega ** 2 * np.asarray(m, dtype=np.float64).reshape(grid.shape) + sgn * 1j * omega * np.asarray(b).reshape(grid.shape)
+    out += diag * v
+    return out.reshape(-1)
+
+
+def helmholtz_rows(grid, m: np.ndarray, omega: float, cells, b: Optional[np.ndarray] = None):
+    """Rows `cells` of A (same operator as `helmholtz`) straight from the
+    stencil: (cols, vals), each of shape (len(cells), 7), the centre first and
+    then the -x, +x, -y, +y, -z, +z neighbours.  A neighbour outside the grid
+    (zero ghost) gets value 0 and the centre as its column."""
+    if b is None:
+        b = sponge(grid)
+    cells = np.asarray(cells, dtype=np.int64).reshape(-1)
+    x = cells % grid.nx
+    y = (cells // grid.nx) % grid.ny
+    z = cells // (grid.nx * grid.ny)
+    h2 = 1.0 / grid.h ** 2
+    mm = np.asarray(m, dtype=np.float64).reshape(-1)
+    bb = np.asarray(b, dtype=np.float64).reshape(-1)
+    cols = np.empty((cells.size, 7), dtype=np.int64)
+    vals = np.zeros((cells.size, 7), dtype=np.complex128)
+    cols[:, 0] = cells
+    vals[:, 0] = -6.0 * h2 + omega ** 2 * mm[cells] - 1j * omega * bb[cells]
+    steps = [(x, grid.nx, 1), (y, grid.ny, grid.nx), (z, grid.nz, grid.nx * grid.ny)]
+    k = 1
+    for coord, n, stride in steps:
+        for dirn in (-1, 1):
+            inside = (coord + dirn >= 0) & (coord + dirn < n)
+            cols[:, k] = np.where(inside, cells + dirn * stride, cells)
+            vals[:, k] = np.where(inside, h2, 0.0)
+            k += 1
+    return cols, vals
+
+
 def restriction(n: int, rec: np.ndarray) -> sp.csr_matrix:
     """P: n_r x n selection of the receiver cells."""
     rec = np.asarray(rec, dtype=np.int64)

@@ -437,3 +437,25 @@ def test_cgls_column_scaling_keeps_minimiser():
         out = oracle.cgls(A, P, s.lam, s.src, "estimate", 0, s.d, rtol=1e-12, maxiter=100000, alpha_scale=c)
         assert np.linalg.norm(out["u"] - u) / np.linalg.norm(u) < 1e-8
         assert abs(out["alpha"] - a) / abs(a) < 1e-8
+
+
+def test_matrix_free_helmholtz_equals_assembled_operator():
+    """The full-size helpers (matrix-free A u, A^H u and single stencil rows)
+    reproduce the assembled sparse operator on a ragged grid with a sponge."""
+    p = wri_synth.custom_problem((7, 5, 6), nb=2, n_src=1, n_rec=3, seed=31)
+    g = p.grids[0]
+    omega = p.systems[0].omega
+    A = oracle.helmholtz(g, p.m[0], omega)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(g.n) + 1j * rng.standard_normal(g.n)
+    assert np.allclose(oracle.helmholtz_apply(g, p.m[0], omega, u), A @ u, rtol=1e-13, atol=1e-12 * np.abs(A @ u).max())
+    AH = A.conj().T.tocsr()
+    assert np.allclose(oracle.helmholtz_apply(g, p.m[0], omega, u, adjoint=True), AH @ u, rtol=1e-13,
+                       atol=1e-12 * np.abs(AH @ u).max())
+    cells = np.array([0, 1, g.nx - 1, g.nx * g.ny + 3, g.n - 1, g.n // 2])
+    cols, vals = oracle.helmholtz_rows(g, p.m[0], omega, cells)
+    dense = A.toarray()
+    for i, c in enumerate(cells):
+        row = np.zeros(g.n, dtype=np.complex128)
+        np.add.at(row, cols[i], vals[i])
+        assert np.allclose(row, dense[c], rtol=1e-14, atol=1e-14 * np.abs(dense[c]).max())
