@@ -198,6 +198,81 @@ int estimate_source(const wri_grid* grids, int32_t n_grids, const float* const* 
 int wri_apply_helmholtz(const wri_grid* grid, const float* m, double omega,
                         const wri_c32* in, wri_c32* out, int32_t adjoint, void* stream);
 
+/* ---- outer loop: source-free adaptive WRI with TV (section "SF-AWRI with
+ * total variation regularization", eq. TVAWRI, Algorithm 2) ---------------- */
+
+/* Smoothed isotropic total variation of a model on one grid:
+ *   TV(m) = sum over cells of sqrt((D_x m)^2 + (D_y m)^2 + (D_z m)^2 + eps^2),
+ * forward differences (D_x m)[i] = (m[i+1] - m[i]) / h, zero in the last cell
+ * of every axis (the paper names the TV norm without defining it).
+ *   m: DEVICE float32 n; value: HOST, TV(m) (float64 sums, fixed order);
+ *   grad: DEVICE float32 n or NULL: grad += gamma * dTV/dm;
+ *   ws: DEVICE workspace of wri_tv_workspace_bytes(grid) bytes.
+ * Synchronises the stream (the value is host memory). */
+size_t wri_tv_workspace_bytes(const wri_grid* grid);
+int wri_tv(const wri_grid* grid, const float* m, double eps, double gamma, double* value, float* grad,
+           void* ws, size_t ws_bytes, void* stream);
+
+/* l-BFGS search direction dir = -H g (two-loop recursion; H_0 = h0 I, or, with
+ * h0 <= 0 and at least one pair, s.y / y.y of the newest pair).
+ *   g, dir: DEVICE float32 n (distinct); S, Y: DEVICE float32 [capacity][n]
+ *   rings of curvature pairs s_i = m_{i+1} - m_i, y_i = g_{i+1} - g_i; the
+ *   `count` pairs in use end at slot `newest` (older pairs in the slots
+ *   before it, cyclically).  Dot products are float64.  Stream-ordered (no
+ *   synchronisation).  ws: DEVICE, wri_lbfgs_workspace_bytes(capacity). */
+size_t wri_lbfgs_workspace_bytes(int32_t capacity);
+int wri_lbfgs_direction(int64_t n, const float* g, const float* S, const float* Y, int32_t capacity,
+                        int32_t count, int32_t newest, double h0, float* dir, void* ws, size_t ws_bytes,
+                        void* stream);
+
+typedef struct {
+  double  gamma;      /* TV weight: the loop minimises F(m) = J(m) + gamma TV(m), J as
+                         returned by wri_objective_grad (the paper's f4 is
+                         (lambda_p^2/2) J + gamma_p TV, i.e. gamma = 2 gamma_p / lambda_p^2) */
+  double  eps_tv;     /* TV smoothing                                                       */
+  double  eps0;       /* initial solver tolerance (relative normal residual, every system)  */
+  double  eps_min;    /* a rejected trial that would halve eps below this ends the loop     */
+  double  step0;      /* first step, before any curvature pair: max|dm| = step0 * max|m|    */
+  double  max_step;   /* every step is scaled to max|dm| <= max_step * max|m| (0: no cap)   */
+  double  m_min, m_max; /* bounds of the squared slowness (<= 0: none)                      */
+  int32_t max_outer;  /* accepted model updates                                             */
+  int32_t memory;     /* curvature pairs kept                                               */
+  int32_t max_iter;   /* CGLS iteration cap per solve                                       */
+  int32_t flags;      /* solver flags (WRI_FLAG_*)                                          */
+  int32_t mask_sponge;/* 1: the damping layer is not updated (gradient zeroed there)        */
+  int32_t reserved_;
+} wri_awri_options;
+
+enum { WRI_AWRI_EVAL = 0, WRI_AWRI_ACCEPTED = 1, WRI_AWRI_REJECTED = 2 };
+
+typedef struct {
+  double  F, J, tv;       /* F = J + gamma TV and its parts at the evaluated model       */
+  double  eps;            /* solver tolerance of the evaluation                          */
+  int32_t kind;           /* WRI_AWRI_EVAL: the current model (start, or again after eps
+                             was halved); _ACCEPTED / _REJECTED: a trial model          */
+  int32_t solver_iters;   /* CGLS iterations summed over the systems                     */
+  double  seconds;        /* wall time of the evaluation (solves, gradient, TV)         */
+} wri_awri_record;
+
+/* Algorithm 2 on one grid: repeat { trial m~ = m - H g (l-BFGS; unit step,
+ * optionally capped and clipped to the bounds); solve and evaluate F at m~
+ * with tolerance eps; if F(m~) <= F(m) accept it, else halve eps, drop the
+ * curvature pairs (formed at the looser tolerance) and evaluate F and g at m
+ * again } until max_outer trials are accepted.  The values at an accepted
+ * trial serve as the next iteration's F and g.
+ *   m: DEVICE float32 n, the start model, overwritten with the result;
+ *   sys: as for wri_objective_grad (every system's rtol is replaced by eps;
+ *   all systems on grid 0); history: HOST, up to history_cap records, one per
+ *   evaluation; *n_records: records produced (more than history_cap means the
+ *   rest were not stored); ws: DEVICE, wri_awri_workspace_bytes(...).
+ * Returns WRI_OK, or WRI_NOT_CONVERGED when the loop stopped at eps_min; the
+ * errors of wri_objective_grad otherwise. */
+size_t wri_awri_workspace_bytes(const wri_grid* grid, const wri_system* sys, int32_t n_sys, int32_t mode,
+                                int32_t flags, int32_t memory);
+int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sys, int32_t mode,
+             const wri_awri_options* opt, wri_awri_record* history, int32_t history_cap,
+             int32_t* n_records, void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel time of the last WRI_FLAG_TIMING call on this thread (HIP event
  * pairs around every fused launch; one launch covers every active system).
  * Bytes are algorithmic: per cell, forward 36 B (+24 B for the x update on

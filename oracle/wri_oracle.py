@@ -430,3 +430,187 @@ def paper_f2(A, P, lam_p, u, alpha, e, d) -> float:
     r1 = A @ u - alpha * e
     r2 = P @ u - d
     return 0.5 * float(np.vdot(r2, r2).real + lam_p ** 2 * np.vdot(r1, r1).real)
+
+
+# --------------------------------------------------------------------------
+# Outer loop: source-free adaptive WRI with TV regularisation
+# (section "SF-AWRI with total variation regularization", eq. TVAWRI,
+#  Algorithm 2)
+# --------------------------------------------------------------------------
+
+def tv(grid, m: np.ndarray, eps: float) -> float:
+    """Smoothed isotropic total variation (the paper names the TV norm without
+    defining it; reading): TV(m) = sum over cells of
+    sqrt((D_x m)^2 + (D_y m)^2 + (D_z m)^2 + eps^2), with forward differences
+    (D_x m)[i] = (m[i+1] - m[i]) / h and a zero difference in the last cell of
+    every axis (the model is not extended past the grid)."""
+    phi, _ = _tv_parts(grid, m, eps)
+    return float(phi.sum())
+
+
+def _tv_parts(grid, m, eps):
+    v = np.asarray(m, dtype=np.float64).reshape(grid.shape)
+    d = []
+    for ax in range(3):
+        dd = np.zeros_like(v)
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(0, -1)
+        hi[ax] = slice(1, None)
+        dd[tuple(lo)] = (v[tuple(hi)] - v[tuple(lo)]) / grid.h
+        d.append(dd)
+    phi = np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + eps ** 2)
+    return phi, d
+
+
+def tv_grad(grid, m: np.ndarray, eps: float) -> np.ndarray:
+    """Gradient of `tv` with respect to m (same shape as m, flattened).
+
+    Cell c enters its own forward differences with weight -1/h and the
+    difference of its lower neighbour along each axis with weight +1/h:
+    dTV/dm_c = (1/h) * sum over axes a of (q_a[c - e_a] - q_a[c]),
+    q_a = (D_a m) / phi (q_a is zero where D_a m is)."""
+    phi, d = _tv_parts(grid, m, eps)
+    out = np.zeros(grid.shape)
+    for ax in range(3):
+        q = d[ax] / phi
+        out -= q
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(0, -1)
+        hi[ax] = slice(1, None)
+        out[tuple(hi)] += q[tuple(lo)]
+    return (out / grid.h).reshape(-1)
+
+
+def lbfgs_two_loop(g: np.ndarray, pairs, h0: float) -> np.ndarray:
+    """H g for the limited-memory BFGS inverse-Hessian approximation built from
+    the curvature pairs (s_i, y_i), oldest first, with H_0 = h0 * I (the
+    two-loop recursion; Nocedal and Wright, Numerical Optimization, Alg. 7.4).
+    The model update of Algorithm 2 is m - H g."""
+    q = np.asarray(g, dtype=np.float64).copy()
+    coef = []
+    for s, y in reversed(pairs):
+        rho = 1.0 / float(np.dot(y, s))
+        a = rho * float(np.dot(s, q))
+        q -= a * y
+        coef.append((rho, a))
+    r = h0 * q
+    for (s, y), (rho, a) in zip(pairs, reversed(coef)):
+        b = rho * float(np.dot(y, r))
+        r += (a - b) * s
+    return r
+
+
+def inexact_objective_grad(problem, m, rtol, mode=None, alpha_scale=None):
+    """J and g at model m with every system solved by the reference CGLS to
+    the relative normal-residual tolerance rtol (complex128).  J and g use the
+    recurred residual r1 = b1 - (A u - alpha e) of CGLS, as the GPU path does:
+    J = sum ||r||^2, g = -sum 2 omega^2 Re(conj(u) r1)."""
+    mode = mode or problem.mode
+    J = 0.0
+    grads = [np.zeros(gr.n) for gr in problem.grids]
+    iters = []
+    for k, s in enumerate(problem.systems):
+        gr = problem.grids[s.grid]
+        A = helmholtz(gr, m[s.grid], s.omega)
+        P = restriction(gr.n, s.rec)
+        c = (np.sqrt(42.0) / gr.h ** 2) if alpha_scale is None else alpha_scale
+        out = cgls(A, P, s.lam, s.src, mode, s.alpha, s.d, rtol=rtol, maxiter=10 ** 6, alpha_scale=c)
+        r = out["r"]
+        J += float(np.vdot(r, r).real)
+        grads[s.grid] += -2.0 * s.omega ** 2 * np.real(np.conj(out["u"]) * r[:gr.n])
+        iters.append(out["iters"])
+    return J, grads, iters
+
+
+def awri(problem, m0, gamma: float, eps0: float, n_outer: int, memory: int = 5, eps_tv: float = 1e-9,
+         step0: float = 0.01, eps_min: float = 1e-8, solver: str = "exact", m_min: float = 0.0,
+         m_max: float = 0.0, max_step: float = 0.0, mask_sponge: bool = False) -> Dict:
+    """Algorithm 2 (source-free AWRI with TV) on a single-grid problem.
+
+    Objective F(m) = J(m) + gamma * TV(m) in this package's scaling
+    (J = sum ||A u - alpha e||^2 + lam^2 ||P u - d||^2; the paper's f4 equals
+    (lambda_p^2 / 2) J + gamma_p TV, so gamma = 2 gamma_p / lambda_p^2).
+    Each trial model is m - H g (l-BFGS, unit step; with no curvature pair
+    yet, H = step0 * max|m| / max|g| * I).  A trial whose F does not decrease
+    halves the solver tolerance eps and recomputes F, g and the l-BFGS
+    approximation at the current model (the paper's "go back"); the
+    curvature pairs collected at the looser tolerance are dropped (reading:
+    they mix gradients of two accuracies, and without a line search a stale
+    pair repeats the same rejected step), so the next trial is a scaled
+    gradient step.  The loop stops when eps would fall below eps_min.  Accepted trials add the pair (s, y) = (dm, dg) when s.y > 0 and
+    keep the last `memory` pairs.  The values at an accepted trial serve as the
+    next iteration's F and g (same model, same tolerance).  Optional bounds
+    clip the trial model to [m_min, m_max] (0 disables a bound).  Two
+    safeguards that the algorithm as printed does not have (readings): the
+    update is scaled down so that max|dm| <= max_step * max|m| (0: no cap), and
+    with mask_sponge the update is zero inside the damping layer (b > 0), which
+    is an extension of the physical model rather than part of it.
+
+    solver: "exact" (sparse direct, eps only drives the schedule) or "cgls"
+    (reference CGLS to tolerance eps, see `inexact_objective_grad`).
+    Returns dict(m, history) with one record per trial:
+    (F, J, TV, eps, accepted, solver iterations)."""
+    grid = problem.grids[0]
+    assert len(problem.grids) == 1
+    m = np.asarray(m0, dtype=np.float64).reshape(-1).copy()
+
+    def evaluate(mm, eps):
+        if solver == "exact":
+            o = objective_grad(problem, [mm.reshape(grid.shape)], return_fields=False)
+            J, g, it = o["J"], o["g"][0].reshape(-1), 0
+        else:
+            J, gl, its = inexact_objective_grad(problem, [mm], eps)
+            g, it = gl[0], int(sum(its))
+        t = tv(grid, mm, eps_tv)
+        gg = g + gamma * tv_grad(grid, mm, eps_tv)
+        if mask_sponge:
+            gg = np.where(sponge(grid) > 0.0, 0.0, gg)
+        return J + gamma * t, gg, J, t, it
+
+    eps = float(eps0)
+    F, g, J, T, it = evaluate(m, eps)
+    history = [dict(F=F, J=J, TV=T, eps=eps, accepted=True, iters=it)]
+    pairs = []
+    accepted = 0
+    while accepted < n_outer:
+        if pairs:
+            s_new, y_new = pairs[-1]
+            h0 = float(np.dot(s_new, y_new) / np.dot(y_new, y_new))
+        else:
+            gmax = float(np.abs(g).max())
+            if gmax == 0.0:
+                break
+            h0 = step0 * float(np.abs(m).max()) / gmax
+        dm = -lbfgs_two_loop(g, pairs, h0)
+        if mask_sponge:
+            dm[sponge(grid) > 0.0] = 0.0
+        if max_step > 0.0:
+            cap = max_step * float(np.abs(m).max())
+            big = float(np.abs(dm).max())
+            if big > cap:
+                dm *= cap / big
+        m_try = m + dm
+        if m_min > 0.0:
+            m_try = np.maximum(m_try, m_min)
+        if m_max > 0.0:
+            m_try = np.minimum(m_try, m_max)
+        F_try, g_try, J_try, T_try, it = evaluate(m_try, eps)
+        ok = F_try <= F
+        history.append(dict(F=F_try, J=J_try, TV=T_try, eps=eps, accepted=ok, iters=it))
+        if not ok:
+            if 0.5 * eps < eps_min:
+                break
+            eps *= 0.5
+            pairs = []
+            F, g, J, T, it = evaluate(m, eps)
+            history.append(dict(F=F, J=J, TV=T, eps=eps, accepted=True, iters=it, reeval=True))
+            continue
+        s, y = m_try - m, g_try - g
+        if float(np.dot(s, y)) > 0.0:
+            pairs.append((s, y))
+            pairs = pairs[-memory:] if memory > 0 else []
+        m, F, g = m_try, F_try, g_try
+        accepted += 1
+    return dict(m=m, history=history)

@@ -918,6 +918,17 @@ int solve_common(const wri_grid* grids, int32_t n_grids, const float* const* m, 
 }
 
 }  // namespace
+
+int report_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
 }  // namespace wri
 
 using namespace wri;

@@ -94,6 +94,9 @@ struct GroupDesc {
   int xchunk;      // tiles per XCD chunk (same value in every entry of a table)
 };
 
+// Records a failure for wri_last_error (thread-local) and returns code.
+int report_error(int code, const char* fmt, ...);
+
 // ---- launchers (kernels.hip) -------------------------------------------
 hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s);
 // Fused CGLS launches over all groups (same tile shape c for all of them).

@@ -72,6 +72,21 @@ class WriTiming(ctypes.Structure):
                 ("reserved_", ctypes.c_int32)]
 
 
+class WriAwriOptions(ctypes.Structure):
+    _fields_ = [("gamma", c_double), ("eps_tv", c_double), ("eps0", c_double), ("eps_min", c_double),
+                ("step0", c_double), ("max_step", c_double), ("m_min", c_double), ("m_max", c_double),
+                ("max_outer", c_int32), ("memory", c_int32), ("max_iter", c_int32), ("flags", c_int32),
+                ("mask_sponge", c_int32), ("reserved_", c_int32)]
+
+
+class WriAwriRecord(ctypes.Structure):
+    _fields_ = [("F", c_double), ("J", c_double), ("tv", c_double), ("eps", c_double), ("kind", c_int32),
+                ("solver_iters", c_int32), ("seconds", c_double)]
+
+
+AWRI_KINDS = {0: "eval", 1: "accepted", 2: "rejected"}
+
+
 class WriError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"wri error {code}: {msg}")
@@ -115,12 +130,29 @@ def lib() -> ctypes.CDLL:
     L.wri_version.restype = c_int
     L.wri_kernel_times.argtypes = [POINTER(WriTiming)]
     L.wri_kernel_times.restype = c_int
+    L.wri_tv_workspace_bytes.argtypes = [POINTER(WriGrid)]
+    L.wri_tv_workspace_bytes.restype = c_size_t
+    L.wri_tv.argtypes = [POINTER(WriGrid), vp, c_double, c_double, POINTER(c_double), vp, vp, c_size_t, vp]
+    L.wri_tv.restype = c_int
+    L.wri_lbfgs_workspace_bytes.argtypes = [c_int32]
+    L.wri_lbfgs_workspace_bytes.restype = c_size_t
+    L.wri_lbfgs_direction.argtypes = [ctypes.c_int64, vp, vp, vp, c_int32, c_int32, c_int32, c_double, vp, vp,
+                                      c_size_t, vp]
+    L.wri_lbfgs_direction.restype = c_int
+    L.wri_awri_workspace_bytes.argtypes = [POINTER(WriGrid), POINTER(WriSystem), c_int32, c_int32, c_int32,
+                                           c_int32]
+    L.wri_awri_workspace_bytes.restype = c_size_t
+    L.wri_awri.argtypes = [POINTER(WriGrid), vp, POINTER(WriSystem), c_int32, c_int32, POINTER(WriAwriOptions),
+                           POINTER(WriAwriRecord), c_int32, POINTER(c_int32), vp, c_size_t, vp]
+    L.wri_awri.restype = c_int
     _lib = L
     return L
 
 
 EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_objective_grad", "estimate_source",
-            "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version")
+            "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version",
+            "wri_tv_workspace_bytes", "wri_tv", "wri_lbfgs_workspace_bytes", "wri_lbfgs_direction",
+            "wri_awri_workspace_bytes", "wri_awri")
 
 
 def kernel_times() -> dict:
@@ -307,3 +339,61 @@ class WRIObjective(torch.autograd.Function):
 def wri_objective(batch: Batch, *ms, mode=None, max_iter=20000, flags=0):
     """Functional form of WRIObjective."""
     return WRIObjective.apply(batch, batch.mode if mode is None else mode, max_iter, flags, *ms)
+
+
+# --------------------------------------------------------------------------
+# outer loop: TV, l-BFGS direction, Algorithm 2 (adaptive tolerance)
+# --------------------------------------------------------------------------
+
+def tv(grid, m: torch.Tensor, eps: float, gamma: float = 0.0, grad: Optional[torch.Tensor] = None) -> float:
+    """Smoothed TV of m (device float32) on `grid` (a wri_synth.Grid);
+    grad (device float32) += gamma * dTV/dm when given."""
+    cg = make_grid(grid)
+    nbytes = lib().wri_tv_workspace_bytes(ctypes.byref(cg))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=m.device)
+    v = c_double(0.0)
+    _check(lib().wri_tv(ctypes.byref(cg), c_void_p(m.data_ptr()), float(eps), float(gamma), ctypes.byref(v),
+                        c_void_p(grad.data_ptr()) if grad is not None else None, c_void_p(ws.data_ptr()),
+                        ws.numel(), _stream(m.device)))
+    return v.value
+
+
+def lbfgs_direction(g: torch.Tensor, S: torch.Tensor, Y: torch.Tensor, count: int, newest: int,
+                    h0: float) -> torch.Tensor:
+    """-H g from the curvature-pair rings S, Y (device float32, [capacity, n])."""
+    cap = int(S.shape[0]) if S is not None else 0
+    nbytes = lib().wri_lbfgs_workspace_bytes(cap)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=g.device)
+    d = torch.empty_like(g)
+    _check(lib().wri_lbfgs_direction(g.numel(), c_void_p(g.data_ptr()),
+                                     c_void_p(S.data_ptr()) if cap else None, c_void_p(Y.data_ptr()) if cap else None,
+                                     cap, int(count), int(newest), float(h0), c_void_p(d.data_ptr()),
+                                     c_void_p(ws.data_ptr()), ws.numel(), _stream(g.device)))
+    return d
+
+
+def awri(batch: Batch, gamma=0.0, eps_tv=1e-9, eps0=1e-3, eps_min=1e-8, step0=0.01, max_step=0.0,
+         m_min=0.0, m_max=0.0, max_outer=10, memory=5, max_iter=20000, flags=0, mask_sponge=True,
+         mode=None, history_cap=4096):
+    """Algorithm 2 on the batch's single grid.  The batch's model tensor is
+    updated in place.  Returns (status code, list of evaluation records)."""
+    if len(batch.grids_py) != 1:
+        raise WriError(EINVAL, "the outer loop runs on one grid")
+    mode = batch.mode if mode is None else mode
+    o = WriAwriOptions(float(gamma), float(eps_tv), float(eps0), float(eps_min), float(step0), float(max_step),
+                       float(m_min), float(m_max), int(max_outer), int(memory), int(max_iter), int(flags),
+                       int(bool(mask_sponge)), 0)
+    nbytes = lib().wri_awri_workspace_bytes(batch.cgrids, batch.csys, batch.nsys, mode, int(flags), int(memory))
+    if nbytes == 0:
+        raise WriError(EINVAL, last_error())
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=batch.device)
+    hist = (WriAwriRecord * max(1, history_cap))()
+    nrec = c_int32(0)
+    code = lib().wri_awri(batch.cgrids, c_void_p(batch.m[0].data_ptr()), batch.csys, batch.nsys, mode,
+                          ctypes.byref(o), hist, int(history_cap), ctypes.byref(nrec), c_void_p(ws.data_ptr()),
+                          ws.numel(), _stream(batch.device))
+    if code < 0:
+        _check(code)
+    recs = [dict(F=hist[i].F, J=hist[i].J, TV=hist[i].tv, eps=hist[i].eps, kind=AWRI_KINDS[hist[i].kind],
+                 iters=hist[i].solver_iters, seconds=hist[i].seconds) for i in range(min(nrec.value, history_cap))]
+    return code, recs

@@ -47,6 +47,9 @@ def test_struct_layout_matches_header():
              offsetof(wri_result, alpha), offsetof(wri_result, alpha_ls));
       printf("%zu %zu %zu %zu\n", sizeof(wri_timing), offsetof(wri_timing, fwd_ms_full),
              offsetof(wri_timing, adj_bytes_full), offsetof(wri_timing, tile_order));
+      printf("%zu %zu %zu %zu %zu %zu\n", sizeof(wri_awri_options), offsetof(wri_awri_options, max_outer),
+             offsetof(wri_awri_options, mask_sponge), sizeof(wri_awri_record), offsetof(wri_awri_record, kind),
+             offsetof(wri_awri_record, seconds));
       return 0;
     }
     """
@@ -63,7 +66,10 @@ def test_struct_layout_matches_header():
                           S.rec.offset, S.d.offset, G.h.offset]
     assert vals[11:15] == [R.relres.offset, R.J.offset, R.alpha.offset, R.alpha_ls.offset]
     Tm = wri.WriTiming
-    assert vals[15:] == [ctypes.sizeof(Tm), Tm.fwd_ms_full.offset, Tm.adj_bytes_full.offset, Tm.tile_order.offset]
+    assert vals[15:19] == [ctypes.sizeof(Tm), Tm.fwd_ms_full.offset, Tm.adj_bytes_full.offset, Tm.tile_order.offset]
+    O, Rr = wri.WriAwriOptions, wri.WriAwriRecord
+    assert vals[19:] == [ctypes.sizeof(O), O.max_outer.offset, O.mask_sponge.offset, ctypes.sizeof(Rr),
+                         Rr.kind.offset, Rr.seconds.offset]
 
 
 def _mk(n_rec=4, dup=False, src=5, rec_bad=False, grid=0, lam=0.1, omega=30.0, rtol=1e-6, nb=2, v_ref=1500.0):
@@ -149,3 +155,35 @@ def test_strerror():
     L = wri.lib()
     for c in (0, 1, -1, -2, -3, -4, -5, -6):
         assert len(L.wri_strerror(c)) > 0
+
+
+def test_outer_loop_entry_points_validate_before_device_work():
+    L = wri.lib()
+    g = (wri.WriGrid * 1)(wri.WriGrid(10, 9, 8, 2, 10.0, 1500.0))
+    v = ctypes.c_double(0.0)
+    assert L.wri_tv(None, ctypes.c_void_p(0x1000), 1e-9, 0.0, ctypes.byref(v), None, None, 0, None) == wri.EINVAL
+    assert L.wri_tv(g, ctypes.c_void_p(0x1000), -1.0, 0.0, ctypes.byref(v), None, None, 0, None) == wri.EINVAL
+    assert L.wri_tv(g, ctypes.c_void_p(0x1000), 1e-9, 0.0, ctypes.byref(v), None, ctypes.c_void_p(0x2000), 8,
+                    None) == wri.ENOWS
+    assert L.wri_tv_workspace_bytes(g) >= 3 * 8 * 720
+    # l-BFGS ring checks
+    p = ctypes.c_void_p(0x1000)
+    assert L.wri_lbfgs_direction(100, p, p, p, 4, 5, 0, 1.0, p, p, 1 << 20, None) == wri.EINVAL
+    assert L.wri_lbfgs_direction(100, p, p, p, 4, 2, 4, 1.0, p, p, 1 << 20, None) == wri.EINVAL
+    assert L.wri_lbfgs_direction(100, p, None, None, 0, 0, 0, 0.0, p, p, 1 << 20, None) == wri.EINVAL
+    assert L.wri_lbfgs_direction(100, p, p, p, 4, 2, 1, 1.0, p, p, 8, None) == wri.ENOWS
+    # driver options
+    gg, s, rec = _mk()
+    o = wri.WriAwriOptions(0.0, 1e-9, 1e-3, 1e-2, 0.01, 0.0, 0.0, 0.0, 3, 2, 100, 0, 1, 0)   # eps_min > eps0
+    n = ctypes.c_int32(0)
+    assert L.wri_awri(gg, p, s, 1, wri.ESTIMATE, ctypes.byref(o), None, 0, ctypes.byref(n), p, 1 << 40,
+                      None) == wri.EINVAL
+    o.eps_min = 1e-6
+    o.m_min, o.m_max = 2e-7, 1e-7
+    assert L.wri_awri(gg, p, s, 1, wri.ESTIMATE, ctypes.byref(o), None, 0, ctypes.byref(n), p, 1 << 40,
+                      None) == wri.EINVAL
+    o.m_min, o.m_max = 0.0, 0.0
+    need = L.wri_awri_workspace_bytes(gg, s, 1, wri.ESTIMATE, 0, 2)
+    assert need > L.wri_workspace_bytes(gg, 1, s, 1, wri.ESTIMATE, 0) + 7 * 4 * 720
+    assert L.wri_awri(gg, p, s, 1, wri.ESTIMATE, ctypes.byref(o), None, 0, ctypes.byref(n), p, need - 1,
+                      None) == wri.ENOWS

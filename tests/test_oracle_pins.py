@@ -459,3 +459,91 @@ def test_matrix_free_helmholtz_equals_assembled_operator():
         row = np.zeros(g.n, dtype=np.complex128)
         np.add.at(row, cols[i], vals[i])
         assert np.allclose(row, dense[c], rtol=1e-14, atol=1e-14 * np.abs(dense[c]).max())
+
+
+# --------------------------------------------------------------------------
+# outer loop: TV, l-BFGS, Algorithm 2
+# --------------------------------------------------------------------------
+
+def test_tv_closed_forms():
+    """Constant model: every cell contributes eps.  A ramp along x: the
+    interior cells contribute sqrt((a/h)^2 + eps^2), the last x-column eps."""
+    g = Grid(7, 5, 4, 10.0, 0, 1500.0)
+    eps = 1e-6
+    assert oracle.tv(g, np.full(g.n, 3.3e-7), eps) == pytest.approx(g.n * eps, rel=1e-12)
+    a = 2.0e-9
+    ramp = (a * np.arange(g.nx))[None, None, :] * np.ones(g.shape)
+    want = (g.nx - 1) * g.ny * g.nz * np.sqrt((a / g.h) ** 2 + eps ** 2) + g.ny * g.nz * eps
+    assert oracle.tv(g, ramp, eps) == pytest.approx(want, rel=1e-12)
+    # the ramp along z instead (axis order check)
+    rz = (a * np.arange(g.nz))[:, None, None] * np.ones(g.shape)
+    want_z = (g.nz - 1) * g.ny * g.nx * np.sqrt((a / g.h) ** 2 + eps ** 2) + g.ny * g.nx * eps
+    assert oracle.tv(g, rz, eps) == pytest.approx(want_z, rel=1e-12)
+
+
+def test_tv_gradient_matches_finite_differences():
+    g = Grid(5, 4, 6, 10.0, 0, 1500.0)
+    rng = np.random.default_rng(5)
+    m = 3e-7 * (1.0 + 0.1 * rng.standard_normal(g.n))
+    eps = 1e-10
+    gr = oracle.tv_grad(g, m, eps)
+    h = 1e-11
+    for c in rng.choice(g.n, 12, replace=False):
+        mp, mm = m.copy(), m.copy()
+        mp[c] += h
+        mm[c] -= h
+        fd = (oracle.tv(g, mp, eps) - oracle.tv(g, mm, eps)) / (2 * h)
+        assert gr[c] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(gr).max())
+    assert np.allclose(oracle.tv_grad(g, np.full(g.n, 2e-7), eps), 0.0)
+
+
+def test_lbfgs_two_loop_secant_and_exact_inverse():
+    """With pairs y = A s the recursion satisfies the secant condition for the
+    newest pair; when the s_i are A-conjugate and span the space, H = A^-1."""
+    rng = np.random.default_rng(2)
+    n = 6
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.linspace(1.0, 9.0, n)
+    A = Q @ np.diag(lam) @ Q.T
+    g = rng.standard_normal(n)
+    assert np.allclose(oracle.lbfgs_two_loop(g, [], 0.37), 0.37 * g)
+    pairs = [(s, A @ s) for s in rng.standard_normal((3, n))]
+    H_y = oracle.lbfgs_two_loop(pairs[-1][1], pairs, 0.5)
+    assert np.allclose(H_y, pairs[-1][0], rtol=1e-12, atol=1e-12)
+    eig_pairs = [(Q[:, i], A @ Q[:, i]) for i in range(n)]
+    Hg = oracle.lbfgs_two_loop(g, eig_pairs, 0.123)
+    assert np.allclose(Hg, np.linalg.solve(A, g), rtol=1e-10, atol=1e-12)
+
+
+def test_inexact_objective_matches_direct_at_tight_tolerance():
+    p = wri_synth.custom_problem((9, 8, 7), nb=2, n_src=2, n_rec=6, seed=41, freqs=(7.0,))
+    ex = oracle.objective_grad(p, return_fields=False)
+    J, g, iters = oracle.inexact_objective_grad(p, p.m, rtol=1e-12)
+    assert J == pytest.approx(ex["J"], rel=1e-8)
+    assert np.allclose(g[0], ex["g"][0].reshape(-1), rtol=1e-6, atol=1e-8 * np.abs(g[0]).max())
+    assert min(iters) > 0
+
+
+def test_awri_outer_loop_behaviour():
+    """Algorithm 2 with exact solves: the first trial moves by step0 * max|m|
+    in the largest-gradient cell, accepted F never increases, and a rejection
+    halves eps and re-evaluates at the same model."""
+    p = wri_synth.custom_problem((10, 9, 8), nb=2, n_src=3, n_rec=12, seed=43, freqs=(6.0, 9.0))
+    m0 = p.m[0].reshape(-1)
+    out = oracle.awri(p, m0, gamma=1e-8, eps0=1e-3, n_outer=3, memory=3, eps_tv=1e-9, step0=0.02)
+    h = out["history"]
+    acc = [r["F"] for r in h if r["accepted"]]
+    assert len(acc) >= 2
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(acc, acc[1:]))
+    # the first trial, by hand: m - (step0 max|m| / max|g|) g with g = gradient of J + gamma TV
+    o = oracle.objective_grad(p, return_fields=False)
+    gfull = o["g"][0].reshape(-1) + 1e-8 * oracle.tv_grad(p.grids[0], m0, 1e-9)
+    step = 0.02 * np.abs(m0).max() / np.abs(gfull).max() * gfull
+    Ftrial = oracle.objective_grad(p, [(m0 - step).reshape(p.grids[0].shape)], return_fields=False)["J"] + \
+        1e-8 * oracle.tv(p.grids[0], m0 - step, 1e-9)
+    assert h[0]["F"] == pytest.approx(o["J"] + 1e-8 * oracle.tv(p.grids[0], m0, 1e-9), rel=1e-12)
+    assert h[1]["F"] == pytest.approx(Ftrial, rel=1e-10)
+    # every rejected trial is followed by a re-evaluation at half the tolerance
+    for i, r in enumerate(h[:-1]):
+        if not r["accepted"]:
+            assert h[i + 1].get("reeval") and h[i + 1]["eps"] == pytest.approx(0.5 * r["eps"])
