@@ -96,6 +96,62 @@ def cpu_baseline(name, systems, mean_iters, seconds, h):
                        f"iterations per solve at rtol 1e-4)")}
 
 
+def awri_bench(name, updates, dev):
+    """Algorithm 2 on one workload, the four settings of the paper's comparison
+    (fixed tight tolerance, fixed loose tolerance, adaptive, adaptive + TV),
+    `updates` accepted model updates each from the same start model."""
+    import torch
+    import wri_synth
+    from paper_2410_18429_amd import wri
+    prob = wri_synth.make_config(name, seed=0)
+    g = prob.grids[0]
+    m0 = torch.as_tensor(np.asarray(prob.m[0], dtype=np.float32).reshape(-1), device=dev)
+    mt = np.asarray(prob.m_true[0], dtype=np.float64).reshape(-1)
+    b = g.nb
+    inner = np.zeros(g.shape, dtype=bool)
+    inner[b:g.nz - b, b:g.ny - b, b:g.nx - b] = True
+    inner = inner.reshape(-1)
+    err = lambda m: float(np.linalg.norm((m - mt)[inner]) / np.linalg.norm(mt[inner]))
+    batch = wri.Batch(prob, device=dev)
+    # TV weight: 2 % of the starting objective
+    J0, _, _ = wri.objective_grad(batch.__class__(prob.with_rtol(1e-6), device=dev))
+    tv0 = wri.tv(g, m0, 1e-9)
+    gamma_tv = 0.02 * J0 / tv0
+    common = dict(step0=0.02, memory=5, max_step=0.05, m_min=1.0 / 5000.0 ** 2, m_max=1.0 / 1400.0 ** 2,
+                  eps_tv=1e-9, mask_sponge=True, max_outer=updates)
+    runs = [("WRI eps 1e-6", dict(eps0=1e-6, eps_min=1e-6, gamma=0.0)),
+            ("WRI eps 4e-4", dict(eps0=4e-4, eps_min=4e-4, gamma=0.0)),
+            ("AWRI eps0 4e-4", dict(eps0=4e-4, eps_min=1e-6, gamma=0.0)),
+            ("AWRI-TV eps0 4e-4", dict(eps0=4e-4, eps_min=1e-6, gamma=gamma_tv))]
+    # warm the solver (autotune, graphs) once
+    wri.objective_grad(batch)
+    out = []
+    for label, kw in runs:
+        batch.set_m([m0.clone()])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, recs = wri.awri(batch, **common, **kw)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        m = batch.m[0].cpu().numpy().astype(np.float64)
+        acc = sum(r["kind"] == "accepted" for r in recs)
+        out.append({"run": label, "seconds": round(secs, 3), "accepted_updates": acc,
+                    "rejected_trials": sum(r["kind"] == "rejected" for r in recs),
+                    "evaluations": len(recs), "cgls_iterations": int(sum(r["iters"] for r in recs)),
+                    "final_eps": recs[-1]["eps"], "F_start": recs[0]["F"], "F_end":
+                    [r["F"] for r in recs if r["kind"] != "rejected"][-1],
+                    "model_error_start": round(err(m0.cpu().numpy().astype(np.float64)), 6),
+                    "model_error_end": round(err(m), 6), "status": int(code)})
+        print(f"[awri] {label}: {secs:.2f} s, {acc} updates, {out[-1]['cgls_iterations']} CGLS iterations, "
+              f"eps {recs[-1]['eps']:.2e}, model error {out[-1]['model_error_start']:.4f} -> "
+              f"{out[-1]['model_error_end']:.4f}", file=sys.stderr, flush=True)
+    base = out[0]["seconds"]
+    print(json.dumps({"metric": "Algorithm 2 outer loop: seconds per run of accepted l-BFGS updates",
+                      "workload": f"{name}: {g.nx}x{g.ny}x{g.nz}, {len(prob.systems)} systems, ESTIMATE",
+                      "updates": updates, "gamma_tv": gamma_tv, "data": "synthetic",
+                      "runs": out, "speedup_vs_tight": {r["run"]: round(base / r["seconds"], 3) for r in out}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +164,10 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=3)
     ap.add_argument("--probe-iters", type=int, default=0,
                     help="counter runs: only run the batch for this many CGLS iterations and exit")
+    ap.add_argument("--awri", action="store_true",
+                    help="outer-loop measurement instead of the headline: Algorithm 2 (adaptive tolerance, "
+                         "l-BFGS, TV) against fixed-tolerance WRI on --config (default medium)")
+    ap.add_argument("--awri-updates", type=int, default=10)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="counter calibration: copy a buffer of this many MiB three times and exit")
     args = ap.parse_args()
@@ -129,6 +189,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return
+    if args.awri:
+        awri_bench("medium" if args.config == "differentiation" else args.config, args.awri_updates, dev)
         return
     prob = wri_synth.make_config(args.config, seed=0)
     g = prob.grids[0]
