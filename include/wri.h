@@ -139,9 +139,17 @@ enum {
   WRI_FLAG_UNSCALED_ALPHA = 8, /* ESTIMATE: use the source column -e exactly as printed
                                (default: -c e with c = sqrt(42)/h^2, same minimiser,
                                better-conditioned iteration) */
-  WRI_FLAG_TIMING = 16      /* launch the batched iterations eagerly with a HIP event
+  WRI_FLAG_TIMING = 16,     /* launch the batched iterations eagerly with a HIP event
                                pair around every fused launch; totals via
                                wri_kernel_times() */
+  WRI_FLAG_WARM_START = 32  /* batched path only: u_out (required, one pointer per
+                               system) holds the initial wavefield on entry, and in
+                               ESTIMATE mode sys[k].alpha the initial source weight.
+                               CGLS starts from x0 = (u0, alpha0) with r0 = b - S x0;
+                               the tolerance stays relative to ||S^H b|| (the
+                               zero-start residual), so the result meets the same
+                               rtol as a cold start.  u0 = 0 reproduces the cold
+                               start bit for bit. */
 };
 
 /* Workspace bytes needed by wri_solve / wri_objective_grad / estimate_source

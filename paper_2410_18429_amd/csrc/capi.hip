@@ -162,6 +162,7 @@ struct Layout {
   std::vector<RecSet> sets;
   size_t off_sysdev = 0, off_state = 0, off_part_d = 0, off_part_s = 0, off_part_j = 0, off_dot = 0;
   size_t off_gdesc = 0;
+  size_t off_nparts = 0;            // per processing slot: partial sums of a set-up pass (warm start)
   std::vector<size_t> off_vec;      // per processing slot: base of its 7 vectors (batched) ; plain: one slot
   std::vector<size_t> off_rvec;     // per processing slot: r2, t2
   std::vector<int> slot_base;       // per processing slot
@@ -224,6 +225,7 @@ Layout make_layout(const wri_grid* grids, int n_grids, const wri_system* sys, in
   L.dot_nparts = dot_parts((int)nmax);
   L.off_dot = take(sizeof(double) * (size_t)(L.dot_nparts * 2 + 16));
   L.off_gdesc = take(sizeof(GroupDesc) * (size_t)std::max(n_grids, 1));
+  L.off_nparts = take(sizeof(int32_t) * (size_t)std::max(n_sys, 1));
   for (auto& rs : L.sets) {
     const wri_grid& g = grids[rs.grid];
     rs.off_rec = take(sizeof(int32_t) * rs.rec.size());
@@ -481,6 +483,22 @@ int launch_setup(Ctx& C) {
   return WRI_OK;
 }
 
+// Warm start (WRI_FLAG_WARM_START): x holds x0.  S^H b gives the reference
+// ||S^H b||^2, then r = b - S x0 and s0 = S^H r.
+int launch_setup_warm(Ctx& C) {
+  WRI_HIP(launch_init(C.dsys, C.dstate, C.n_sys, C.st, 1));
+  WRI_HIP(launch_adj(cur_cfg(C), C.dsys, C.dstate, C.part_d, C.part_s, C.dgd, (int)C.hgd.size(), C.nblocks, C.st));
+  std::vector<int32_t> np(C.n_sys);
+  for (size_t gi = 0; gi < C.hgd.size(); ++gi)
+    for (int r = 0; r < C.hgd[gi].nrhs; ++r) np[C.hgd[gi].rhs0 + r] = C.hgd[gi].ntiles;
+  int32_t* dnp = at<int32_t>(C.ws, C.L.off_nparts);
+  WRI_HIP(hipMemcpyAsync(dnp, np.data(), sizeof(int32_t) * np.size(), hipMemcpyHostToDevice, C.st));
+  WRI_HIP(launch_warm_residual(C.dsys, C.dstate, C.part_s, dnp, C.n_sys, C.st));
+  WRI_HIP(launch_adj(cur_cfg(C), C.dsys, C.dstate, C.part_d, C.part_s, C.dgd, (int)C.hgd.size(), C.nblocks, C.st));
+  WRI_HIP(hipStreamSynchronize(C.st));  // np is host memory
+  return WRI_OK;
+}
+
 bool verbose() {
   static const bool v = [] { const char* e = getenv("WRI_VERBOSE"); return e && *e && *e != '0'; }();
   return v;
@@ -600,20 +618,27 @@ int get_graph(Ctx& C, int64_t k0, int chunk, hipGraphExec_t* out) {
 
 int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
   const Layout& L = C.L;
+  const bool warm = (C.flags & WRI_FLAG_WARM_START) != 0;
   C.hsys.resize(C.n_sys);
-  for (int p = 0; p < C.n_sys; ++p) {
-    const int i = L.order[p];
-    const wri_system& s = C.sys[i];
-    const size_t vb = align_up(sizeof(float2) * (size_t)cells(C.grids[s.grid]));
-    char* base = C.ws + L.off_vec[p];
-    float2* v[7];
-    for (int q = 0; q < 7; ++q) v[q] = reinterpret_cast<float2*>(base + q * vb);
-    float2* x = (C.u_out != nullptr && C.u_out[i] != nullptr) ? reinterpret_cast<float2*>(C.u_out[i]) : v[0];
-    const size_t rb = align_up(sizeof(float2) * (size_t)s.n_rec);
-    float2* r2 = reinterpret_cast<float2*>(C.ws + L.off_rvec[p]);
-    float2* t2 = reinterpret_cast<float2*>(C.ws + L.off_rvec[p] + rb);
-    fill_sysdev(C, p, C.hsys[p], x, v[1], v[2], v[3], v[4], v[5], v[6], r2, t2);
-  }
+  // user_x = 1: x is the caller's u_out where given; 0: the workspace vector
+  // (the autotuner of a warm start must not overwrite the initial guess)
+  auto fill_tables = [&](bool user_x) {
+    for (int p = 0; p < C.n_sys; ++p) {
+      const int i = L.order[p];
+      const wri_system& s = C.sys[i];
+      const size_t vb = align_up(sizeof(float2) * (size_t)cells(C.grids[s.grid]));
+      char* base = C.ws + L.off_vec[p];
+      float2* v[7];
+      for (int q = 0; q < 7; ++q) v[q] = reinterpret_cast<float2*>(base + q * vb);
+      float2* x = (user_x && C.u_out != nullptr && C.u_out[i] != nullptr) ? reinterpret_cast<float2*>(C.u_out[i])
+                                                                          : v[0];
+      const size_t rb = align_up(sizeof(float2) * (size_t)s.n_rec);
+      float2* r2 = reinterpret_cast<float2*>(C.ws + L.off_rvec[p]);
+      float2* t2 = reinterpret_cast<float2*>(C.ws + L.off_rvec[p] + rb);
+      fill_sysdev(C, p, C.hsys[p], x, v[1], v[2], v[3], v[4], v[5], v[6], r2, t2);
+    }
+  };
+  fill_tables(!warm);
   // groups: consecutive processing slots on one grid
   C.groups.clear();
   for (int p = 0; p < C.n_sys; ++p) {
@@ -631,12 +656,16 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     else if (!(C.flags & WRI_FLAG_NO_AUTOTUNE)) rc = autotune(C);
     else rc = set_config(C, kCands[0]);
     if (rc != WRI_OK) return rc;
+    if (warm) {  // the tuned tile is known; now point x at the caller's initial guess
+      fill_tables(true);
+      WRI_HIP(hipMemcpyAsync(C.dsys, C.hsys.data(), sizeof(SysDev) * C.n_sys, hipMemcpyHostToDevice, C.st));
+    }
     if (verbose())
       for (size_t gi = 0; gi < C.groups.size(); ++gi)
         fprintf(stderr, "[wri] grid %d (%d systems): tile w=%d ry=%d tz=%d pf=%d order=%d, %d tiles per system\n",
                 C.groups[gi].grid, C.groups[gi].nrhs, C.tiling[gi].cfg.w, C.tiling[gi].cfg.ry, C.tiling[gi].cfg.tz,
                 C.tiling[gi].cfg.pf, C.tiling[gi].cfg.order, C.tiling[gi].ntiles());
-    rc = launch_setup(C);
+    rc = warm ? launch_setup_warm(C) : launch_setup(C);
     if (rc != WRI_OK) return rc;
     const bool timing = (C.flags & WRI_FLAG_TIMING) != 0;
     const bool use_graph = !(C.flags & WRI_FLAG_NO_GRAPH) && !timing;
@@ -865,6 +894,12 @@ int solve_common(const wri_grid* grids, int32_t n_grids, const float* const* m, 
   if (grad != nullptr)
     for (int g = 0; g < n_grids; ++g)
       if (grad[g] == nullptr) return fail(WRI_EINVAL, "grad[%d] is NULL", g);
+  if (flags & WRI_FLAG_WARM_START) {
+    if (flags & WRI_FLAG_PLAIN) return fail(WRI_EINVAL, "WRI_FLAG_WARM_START is for the batched path only");
+    if (n_sys > 0 && u_out == nullptr) return fail(WRI_EINVAL, "WRI_FLAG_WARM_START needs u_out (the initial guess)");
+    for (int i = 0; i < n_sys; ++i)
+      if (u_out[i] == nullptr) return fail(WRI_EINVAL, "WRI_FLAG_WARM_START: u_out[%d] is NULL", i);
+  }
   Ctx C;
   C.grids = grids; C.n_grids = n_grids; C.m = m; C.sys = sys; C.n_sys = n_sys;
   C.mode = mode; C.max_iter = max_iter; C.flags = flags; C.u_out = u_out;

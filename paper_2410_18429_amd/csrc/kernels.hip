@@ -170,13 +170,14 @@ __device__ __forceinline__ double norm2d(float2 v) {
 // r2 = lambda d, state reset.  grid = (blocks per system, nsys).
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, SysState* __restrict__ stv) {
+__global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, SysState* __restrict__ stv,
+                                              int warm) {
   const int rhs = blockIdx.y;
   const SysDev& S = sysv[rhs];
   const int n = S.nx * S.ny * S.nz;
   const float2 z = f2(0.f, 0.f);
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-    S.x[c] = z;
+    if (!warm) S.x[c] = z;
     S.p[0][c] = z;
     float2 r = z;
     if (S.mode == 0 && c == S.src) r = f2((float)S.alpha.x, (float)S.alpha.y);
@@ -194,7 +195,9 @@ __global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, S
       T->gmin[0] = T->gmin[1] = 0.0;
       T->gamma0 = 0.0;
       T->a[0] = T->a[1] = 0.0;
-      T->xa = make_double2(0.0, 0.0);
+      // warm start in ESTIMATE mode: the unknown is alpha / c
+      T->xa = (warm && S.mode == 1) ? make_double2(S.alpha.x / S.alpha_c, S.alpha.y / S.alpha_c)
+                                    : make_double2(0.0, 0.0);
       T->pa = make_double2(0.0, 0.0);
       T->sa = make_double2(0.0, 0.0);
       T->J = 0.0;
@@ -204,13 +207,79 @@ __global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, S
       T->status = kActive;
       T->iters = 0;
       T->brk = 0;
+      T->warm = warm;
     }
   }
 }
 
-hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s) {
+hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s, int warm) {
   if (nsys <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init, dim3(256, nsys), dim3(256), 0, s, sys, st);
+  hipLaunchKernelGGL(k_init, dim3(256, nsys), dim3(256), 0, s, sys, st, warm);
+  return hipGetLastError();
+}
+
+// Warm start, after a set-up adjoint pass on r = b: gamma0 = ||S^H b||^2 from
+// that pass's partials (summed by one wave in a fixed order), then
+// r1 = b1 - (A x0 - c xa e) and r2 = lambda (d - P x0).  b = 0 (gamma0 = 0)
+// has the solution 0: x0 and xa are zeroed instead, so the solve ends with the
+// zero-right-hand-side status.  grid = (blocks, nsys).
+__global__ void __launch_bounds__(256) k_warm_residual(const SysDev* __restrict__ sysv, SysState* __restrict__ stv,
+                                                      const double* __restrict__ part_s,
+                                                      const int* __restrict__ nparts) {
+  __shared__ double g0s;
+  const int rhs = blockIdx.y;
+  const SysDev& S = sysv[rhs];
+  SysState* T = stv + rhs;
+  if (threadIdx.x < 64) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nparts[rhs]; i += 64) v += part_s[S.slot_base + i];
+    v = wave_sum(v);
+    if (threadIdx.x == 0) g0s = v;
+  }
+  __syncthreads();
+  const double g0 = g0s;
+  const double2 xa = T->xa;  // read by every block before block 0 may clear it
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    T->gamma0 = g0;
+    if (g0 == 0.0) T->xa = make_double2(0.0, 0.0);
+  }
+  const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny, n = plane * nz;
+  const float2 z = f2(0.f, 0.f);
+  const double w2 = S.omega_d * S.omega_d;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    if (g0 == 0.0) {
+      S.x[c] = z;
+      continue;
+    }
+    const int x = c % nx, y = (c / nx) % ny, zz = c / plane;
+    const float2 xc = S.x[c];
+    const float2 xm = x > 0 ? S.x[c - 1] : z, xp = x + 1 < nx ? S.x[c + 1] : z;
+    const float2 ym = y > 0 ? S.x[c - nx] : z, yp = y + 1 < ny ? S.x[c + nx] : z;
+    const float2 zm = zz > 0 ? S.x[c - plane] : z, zp = zz + 1 < nz ? S.x[c + plane] : z;
+    const double b = S.sp_scale_d * (sponge_axis_d(x, nx, S.nb, S.inv_nb_d) + sponge_axis_d(y, ny, S.nb, S.inv_nb_d) +
+                                     sponge_axis_d(zz, nz, S.nb, S.inv_nb_d));
+    double2 ax = helm(xc, xm, xp, ym, yp, zm, zp, S.h2inv_d, w2 * (double)S.m[c], -(S.omega_d * b));
+    if (S.mode == 1 && c == S.src) {  // the source column: A x - c xa e
+      ax.x -= S.alpha_c * xa.x;
+      ax.y -= S.alpha_c * xa.y;
+    }
+    const float2 r = S.r[1][c];
+    S.r[1][c] = f2((float)((double)r.x - ax.x), (float)((double)r.y - ax.y));
+  }
+  if (blockIdx.x == 0 && g0 != 0.0) {
+    for (int q = threadIdx.x; q < S.n_rec; q += blockDim.x) {
+      const float2 xq = S.x[S.rec[q]];
+      const float2 r2 = S.r2[q];
+      S.r2[q] = f2((float)((double)r2.x - S.lam_d * (double)xq.x), (float)((double)r2.y - S.lam_d * (double)xq.y));
+    }
+  }
+}
+
+hipError_t launch_warm_residual(const SysDev* sys, SysState* st, const double* part_s, const int* nparts, int nsys,
+                                hipStream_t s) {
+  if (nsys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_warm_residual, dim3(256, nsys), dim3(256), 0, s, sys, st, part_s, nparts);
   return hipGetLastError();
 }
 
@@ -308,7 +377,8 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   const int k = T->iterA;
 
   const double gk = block_sum_slots<W>(part_s + S.slot_base, ntiles, red);
-  const double g0 = (k == 0) ? gk : T->gamma0;
+  const bool warm = T->warm != 0;  // gamma0 = ||S^H b||^2 was set by the warm-start set-up
+  const double g0 = (k == 0 && !warm) ? gk : T->gamma0;
   const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
   // brk: the adjoint launch of this same k broke down; this launch only finishes x
   const bool brk = T->brk != 0;
@@ -324,7 +394,7 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   if (tile == 0 && tid == 0) {
     T->gamma[k & 1] = gk;
     T->gmin[k & 1] = fmin(gmin, gk);
-    if (k == 0) T->gamma0 = gk;
+    if (k == 0 && !warm) T->gamma0 = gk;
     T->iterB = k;
   }
 
@@ -760,7 +830,8 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   const int k = T->iterA;
 
   const double gk = block_sum_slots<W>(part_s + S.slot_base, ntiles, red);
-  const double g0 = (k == 0) ? gk : T->gamma0;
+  const bool warm = T->warm != 0;  // gamma0 = ||S^H b||^2 was set by the warm-start set-up
+  const double g0 = (k == 0 && !warm) ? gk : T->gamma0;
   const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
   // brk: the adjoint launch of this same k broke down; this launch only finishes x
   const bool brk = T->brk != 0;
@@ -776,7 +847,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   if (tile == 0 && tid == 0) {
     T->gamma[k & 1] = gk;
     T->gmin[k & 1] = fmin(gmin, gk);
-    if (k == 0) T->gamma0 = gk;
+    if (k == 0 && !warm) T->gamma0 = gk;
     T->iterB = k;
   }
 

@@ -69,7 +69,8 @@ struct SysState {
   int iters;
   int brk;            // set by the adjoint kernel on a breakdown; the next pair of
                       // launches finishes x and records the status
-  int pad_[3];
+  int warm;           // warm start: gamma0 holds ||S^H b||^2 from the set-up, not ||S^H r_0||^2
+  int pad_[2];
 };
 
 struct TileCfg {
@@ -98,7 +99,11 @@ struct GroupDesc {
 int report_error(int code, const char* fmt, ...);
 
 // ---- launchers (kernels.hip) -------------------------------------------
-hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s);
+hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s, int warm = 0);
+// Warm start, after a set-up adjoint pass on r = b: gamma0 = ||S^H b||^2 from the
+// pass's partials (nparts per system), then r = b - S x0 (x0 = 0 when b = 0).
+hipError_t launch_warm_residual(const SysDev* sys, SysState* st, const double* part_s, const int* nparts,
+                                int nsys, hipStream_t s);
 // Fused CGLS launches over all groups (same tile shape c for all of them).
 // k: the iteration every active system of the launch is at (systems of one
 // call iterate in lockstep); selects the variant of the forward kernel that

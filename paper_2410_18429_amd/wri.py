@@ -26,6 +26,7 @@ FLAG_NO_GRAPH = 2
 FLAG_NO_AUTOTUNE = 4
 FLAG_UNSCALED_ALPHA = 8
 FLAG_TIMING = 16
+FLAG_WARM_START = 32
 
 
 def alpha_scale(h: float) -> float:
@@ -214,6 +215,12 @@ class Batch:
 
     def set_m(self, m_list):
         self.m = [mm.to(self.device, torch.float32).contiguous().reshape(-1) for mm in m_list]
+
+    def set_alpha(self, alphas):
+        """Per-system source weights: the known weight (KNOWN mode) or the
+        initial guess of a warm start (ESTIMATE mode)."""
+        for k, a in enumerate(alphas):
+            self.csys[k].alpha = WriC64(float(np.real(a)), float(np.imag(a)))
 
     def set_rtol(self, rtol):
         r = [rtol] * self.nsys if np.isscalar(rtol) else list(rtol)

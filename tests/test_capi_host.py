@@ -187,3 +187,20 @@ def test_outer_loop_entry_points_validate_before_device_work():
     assert need > L.wri_workspace_bytes(gg, 1, s, 1, wri.ESTIMATE, 0) + 7 * 4 * 720
     assert L.wri_awri(gg, p, s, 1, wri.ESTIMATE, ctypes.byref(o), None, 0, ctypes.byref(n), p, need - 1,
                       None) == wri.ENOWS
+
+
+def test_warm_start_flag_validation():
+    L = wri.lib()
+    g, s, rec = _mk()
+    res = (wri.WriResult * 1)()
+    m = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x2000))
+    ws = ctypes.c_void_p(0x3000)
+    code = L.wri_solve(g, 1, m, s, 1, wri.ESTIMATE, 10, wri.FLAG_WARM_START, None, res, ws, 1 << 40, None)
+    assert code == wri.EINVAL and "u_out" in wri.last_error()
+    u = (ctypes.c_void_p * 1)(None)
+    code = L.wri_solve(g, 1, m, s, 1, wri.ESTIMATE, 10, wri.FLAG_WARM_START, u, res, ws, 1 << 40, None)
+    assert code == wri.EINVAL
+    u = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x4000))
+    code = L.wri_solve(g, 1, m, s, 1, wri.ESTIMATE, 10, wri.FLAG_WARM_START | wri.FLAG_PLAIN, u, res, ws, 1 << 40,
+                       None)
+    assert code == wri.EINVAL and "batched" in wri.last_error()

@@ -529,3 +529,97 @@ def test_estimate_source_entry_point():
         assert e < 1e-4
         assert alpha2[k] == alpha[k]
         assert rel(_np(u[k]), ref["u"][k]) < 1e-4
+
+
+# --------------------------------------------------------------------------
+# warm start (WRI_FLAG_WARM_START)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+def test_warm_start_from_zero_is_the_cold_start(mode):
+    """u0 = 0 (and alpha0 = 0): r0 = b, the reference is ||S^H b||, so the
+    iterations are the cold start's bit for bit."""
+    _say(f"warm start from zero, {mode}")
+    p = wri_synth.custom_problem((40, 30, 20), nb=3, n_src=3, n_rec=9, seed=8, freqs=(5.0, 8.0), rtol=1e-5)
+    b = wri.Batch(p, device=DEV, mode=mode)
+    uc, rc = wri.solve(b)
+    if mode == "estimate":
+        b.set_alpha([0.0] * len(p.systems))
+    u0 = [torch.zeros_like(u) for u in uc]
+    uw, rw = wri.solve(b, flags=wri.FLAG_WARM_START, u_out=u0)
+    for i in range(len(p.systems)):
+        assert rw[i]["iters"] == rc[i]["iters"]
+        assert torch.equal(uw[i], uc[i])
+        assert rw[i]["alpha"] == rc[i]["alpha"]
+
+
+def test_warm_start_from_the_solution_and_from_a_nearby_model():
+    """Warm start from a converged solution needs only a few iterations (the
+    solve stopped on its recurred residual; the warm start rebuilds the true
+    residual of the stored float32 solution, which lies just above the
+    tolerance) and leaves u essentially unchanged; from the solution at a
+    perturbed model it needs fewer iterations than a cold start and still
+    matches the exact minimiser at the new model."""
+    _say("warm start: converged and nearby")
+    rt = 1e-6
+    p = wri_synth.custom_problem((24, 22, 20), nb=3, n_src=2, n_rec=9, seed=9, freqs=(6.0,), rtol=rt)
+    b = wri.Batch(p, device=DEV)
+    u1, r1 = wri.solve(b)
+    b.set_alpha([r["alpha"] for r in r1])
+    u_again = [u.clone() for u in u1]
+    u2, r2 = wri.solve(b, flags=wri.FLAG_WARM_START, u_out=u_again)
+    for i in range(len(p.systems)):
+        _say(f"  sys {i}: cold {r1[i]['iters']} iterations, warm from its solution {r2[i]['iters']}; "
+             f"u change {rel(_np(u2[i]), _np(u1[i])):.2e}")
+        assert r2[i]["status"] == "converged" and r2[i]["iters"] <= max(10, 0.02 * r1[i]["iters"])
+        assert rel(_np(u2[i]), _np(u1[i])) < 1e-5
+    # a 0.5 % smooth model change
+    g = p.grids[0]
+    zz, yy, xx = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    bump = 1.0 + 0.005 * np.exp(-((xx - 12) ** 2 + (yy - 11) ** 2 + (zz - 10) ** 2) / 30.0)
+    m2 = (p.m[0] * bump).astype(np.float32)
+    p2 = wri_synth.Problem(p.name, p.grids, [m2], p.m_true, p.systems, p.mode, p.max_iter)
+    b2 = wri.Batch(p2, device=DEV)
+    uc, rc = wri.solve(b2)
+    ref = oracle.objective_grad(p2)
+    errs = {}
+    for rt2 in (rt, 1e-7):
+        b2.set_rtol(rt2)
+        b2.set_alpha([r["alpha"] for r in r1])
+        uw, rw = wri.solve(b2, flags=wri.FLAG_WARM_START, u_out=[u.clone() for u in u1])
+        for i in range(len(p.systems)):
+            A, P, e = oracle.system_operators(p2, i)
+            s = p2.systems[i]
+            tr = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d, _np(uw[i]), rw[i]["alpha"])
+            trc = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d, _np(uc[i]), rc[i]["alpha"])
+            err = rel(_np(uw[i]), ref["u"][i])
+            errs[(rt2, i)] = err
+            _say(f"  rtol {rt2:.0e} sys {i}: cold {rc[i]['iters']} iterations (u err "
+                 f"{rel(_np(uc[i]), ref['u'][i]):.2e}, true normal residual {trc:.2e}), warm {rw[i]['iters']} "
+                 f"(u err {err:.2e}, true normal residual {tr:.2e}, relres {rw[i]['relres']:.2e})")
+            assert rw[i]["status"] == "converged" and rw[i]["relres"] <= rt2
+            # the true float64 normal residual is at the cold start's float32 floor
+            # (that floor varies by a few times between runs and systems)
+            assert tr <= max(3 * rt2, 5 * trc)
+            if rt2 == rt:
+                assert rw[i]["iters"] < rc[i]["iters"]
+    # The stopping rule bounds ||S^H r||, which weighs error components along
+    # small singular values of S lightly; a warm start begins with exactly such
+    # components (a smooth model change), so at one rtol its u error can exceed
+    # the cold start's.  Tightening rtol removes them.
+    for i in range(len(p.systems)):
+        assert errs[(1e-7, i)] < 0.2 * errs[(rt, i)] or errs[(1e-7, i)] < 1e-4
+
+
+def test_warm_start_zero_data_gives_zero():
+    _say("warm start, zero data")
+    p = wri_synth.custom_problem((20, 10, 8), nb=2, n_src=2, n_rec=5, seed=12)
+    p = p.with_data([np.zeros_like(s.d) for s in p.systems])
+    b = wri.Batch(p, device=DEV)
+    b.set_alpha([1.0 + 1.0j] * len(p.systems))
+    u0 = [torch.randn(g, dtype=torch.complex64, device=DEV) for g in [b.grid_cells(0)] * len(p.systems)]
+    u, res = wri.solve(b, flags=wri.FLAG_WARM_START, u_out=u0)
+    for i in range(len(p.systems)):
+        assert res[i]["status"] == "zero_rhs" and res[i]["iters"] == 0
+        assert not torch.any(u[i] != 0)
+        assert res[i]["alpha"] == 0
