@@ -122,7 +122,9 @@ def awri_bench(name, updates, dev):
     runs = [("WRI eps 1e-6", dict(eps0=1e-6, eps_min=1e-6, gamma=0.0)),
             ("WRI eps 4e-4", dict(eps0=4e-4, eps_min=4e-4, gamma=0.0)),
             ("AWRI eps0 4e-4", dict(eps0=4e-4, eps_min=1e-6, gamma=0.0)),
-            ("AWRI-TV eps0 4e-4", dict(eps0=4e-4, eps_min=1e-6, gamma=gamma_tv))]
+            ("AWRI-TV eps0 4e-4", dict(eps0=4e-4, eps_min=1e-6, gamma=gamma_tv)),
+            ("AWRI-TV eps0 4e-4, warm start", dict(eps0=4e-4, eps_min=1e-6, gamma=gamma_tv, warm_start=True)),
+            ("WRI eps 1e-6, warm start", dict(eps0=1e-6, eps_min=1e-6, gamma=0.0, warm_start=True))]
     # warm the solver (autotune, graphs) once
     wri.objective_grad(batch)
     out = []
@@ -167,7 +169,7 @@ def main():
     ap.add_argument("--awri", action="store_true",
                     help="outer-loop measurement instead of the headline: Algorithm 2 (adaptive tolerance, "
                          "l-BFGS, TV) against fixed-tolerance WRI on --config (default medium)")
-    ap.add_argument("--awri-updates", type=int, default=10)
+    ap.add_argument("--awri-updates", type=int, default=20)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="counter calibration: copy a buffer of this many MiB three times and exit")
     args = ap.parse_args()

@@ -248,7 +248,8 @@ typedef struct {
   int32_t max_iter;   /* CGLS iteration cap per solve                                       */
   int32_t flags;      /* solver flags (WRI_FLAG_*)                                          */
   int32_t mask_sponge;/* 1: the damping layer is not updated (gradient zeroed there)        */
-  int32_t reserved_;
+  int32_t warm_start; /* 1: every solve after the first starts from the wavefields and
+                         source weights of the current model (WRI_FLAG_WARM_START)      */
 } wri_awri_options;
 
 enum { WRI_AWRI_EVAL = 0, WRI_AWRI_ACCEPTED = 1, WRI_AWRI_REJECTED = 2 };
@@ -274,7 +275,9 @@ typedef struct {
  *   evaluation; *n_records: records produced (more than history_cap means the
  *   rest were not stored); ws: DEVICE, wri_awri_workspace_bytes(...).
  * Returns WRI_OK, or WRI_NOT_CONVERGED when the loop stopped at eps_min; the
- * errors of wri_objective_grad otherwise. */
+ * errors of wri_objective_grad otherwise.  The workspace query takes the
+ * solver flags; add WRI_FLAG_WARM_START to them when opt->warm_start is set
+ * (two wavefield sets of n_sys systems are then part of the workspace). */
 size_t wri_awri_workspace_bytes(const wri_grid* grid, const wri_system* sys, int32_t n_sys, int32_t mode,
                                 int32_t flags, int32_t memory);
 int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sys, int32_t mode,

@@ -293,9 +293,9 @@ int lbfgs_run(int64_t n, const float* g, const float* S, const float* Y, int cap
 
 // ---- the adaptive-tolerance driver (Algorithm 2) ------------------------------------
 struct AwriLayout {
-  size_t solver = 0, off_vec = 0, off_tv = 0, off_lb = 0, off_red = 0, total = 0;
+  size_t solver = 0, off_vec = 0, off_tv = 0, off_lb = 0, off_red = 0, off_u = 0, total = 0;
 };
-AwriLayout awri_layout(int64_t n, size_t solver_bytes, int memory) {
+AwriLayout awri_layout(int64_t n, size_t solver_bytes, int memory, int n_sys, bool warm) {
   AwriLayout L;
   L.solver = al(solver_bytes);
   L.off_vec = L.solver;
@@ -307,6 +307,8 @@ AwriLayout awri_layout(int64_t n, size_t solver_bytes, int memory) {
   off += lb_ws_bytes(std::max(memory, 1));
   L.off_red = off;
   off += al(sizeof(float) * kRedBlocks) + al(sizeof(double) * kRedBlocks);
+  L.off_u = off;  // warm start: wavefields at the current model, then at the trial model
+  if (warm) off += 2 * (size_t)std::max(n_sys, 0) * al(sizeof(float) * 2 * n);
   L.total = off + 256;
   return L;
 }
@@ -382,7 +384,8 @@ size_t wri_awri_workspace_bytes(const wri_grid* grid, const wri_system* sys, int
   if (grid == nullptr || memory < 0) return 0;
   const size_t sb = wri_workspace_bytes(grid, 1, sys, n_sys, mode, flags);
   if (sb == 0) return 0;
-  return awri_layout((int64_t)grid->nx * grid->ny * grid->nz, sb, memory).total;
+  return awri_layout((int64_t)grid->nx * grid->ny * grid->nz, sb, memory, n_sys,
+                     (flags & WRI_FLAG_WARM_START) != 0).total;
 }
 
 int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sys, int32_t mode,
@@ -400,7 +403,8 @@ int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sy
   const size_t sb = wri_workspace_bytes(grid, 1, sys, n_sys, mode, o.flags);
   if (sb == 0) return report_error(WRI_EINVAL, "invalid grid or systems: %s", wri_last_error());
   const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
-  const AwriLayout L = awri_layout(n, sb, o.memory);
+  const bool warm = o.warm_start != 0;
+  const AwriLayout L = awri_layout(n, sb, o.memory, n_sys, warm);
   if (ws == nullptr || ws_bytes < L.total)
     return report_error(WRI_ENOWS, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.total);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -423,21 +427,45 @@ int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sy
 
   std::vector<wri_system> se(sys, sys + n_sys);
   std::vector<wri_result> res(std::max(n_sys, 1));
+  // warm start: wavefields (and source weights) of the current model and of the trial
+  const size_t ub = al(sizeof(float) * 2 * n);
+  std::vector<wri_c32*> ucur(n_sys), utry(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    ucur[i] = reinterpret_cast<wri_c32*>(base + L.off_u + (size_t)i * ub);
+    utry[i] = reinterpret_cast<wri_c32*>(base + L.off_u + (size_t)(n_sys + i) * ub);
+  }
+  std::vector<wri_c64> acur(n_sys), atry(n_sys);
+  bool have_cur = false;
   int recs = 0;
   auto record = [&](double F, double J, double T, double eps, int kind, int iters, double secs) {
     if (recs < history_cap) history[recs] = wri_awri_record{F, J, T, eps, kind, iters, secs};
     ++recs;
   };
-  // F = J + gamma TV and its gradient (masked in the sponge) at model mm, tolerance eps
-  auto evaluate = [&](const float* mm, double eps, float* grad, double* F, double* J, double* T, int* iters,
-                      double* secs) -> int {
+  // F = J + gamma TV and its gradient (masked in the sponge) at model mm, tolerance eps.
+  // Warm start: the solves start from the current model's wavefields `from`
+  // (copied into `into` unless they are the same set) and source weights.
+  auto evaluate_w = [&](const float* mm, double eps, float* grad, double* F, double* J, double* T, int* iters,
+                        double* secs, std::vector<wri_c32*>* into, std::vector<wri_c32*>* from,
+                        std::vector<wri_c64>* alphas_out) -> int {
     const auto t0 = std::chrono::steady_clock::now();
-    for (auto& s : se) s.rtol = eps;
+    int fl = o.flags & ~WRI_FLAG_WARM_START;  // the driver decides per solve
+    for (int i = 0; i < n_sys; ++i) {
+      se[i].rtol = eps;
+      if (warm && have_cur && mode == WRI_ESTIMATE) se[i].alpha = acur[i];
+    }
+    if (warm && have_cur) {
+      fl |= WRI_FLAG_WARM_START;
+      if (from != into)
+        for (int i = 0; i < n_sys; ++i)
+          OUTER_HIP(hipMemcpyAsync((*into)[i], (*from)[i], sizeof(float) * 2 * n, hipMemcpyDeviceToDevice, st));
+    }
     const float* mp[1] = {mm};
     float* gp[1] = {grad};
-    int rc = wri_objective_grad(grid, 1, mp, se.data(), n_sys, mode, o.max_iter, o.flags, J, gp, nullptr,
-                                res.data(), solver_ws, sb, stream);
+    int rc = wri_objective_grad(grid, 1, mp, se.data(), n_sys, mode, o.max_iter, fl, J, gp,
+                                warm ? into->data() : nullptr, res.data(), solver_ws, sb, stream);
     if (rc < 0) return rc;
+    if (warm)
+      for (int i = 0; i < n_sys; ++i) (*alphas_out)[i] = res[i].alpha;
     int it = 0;
     for (int i = 0; i < n_sys; ++i) it += res[i].iters;
     *iters = it;
@@ -453,6 +481,13 @@ int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sy
     return WRI_OK;
   };
 
+  // the current model (start, or again after eps was halved): warm from its own wavefields
+  auto evaluate = [&](const float* mm, double eps, float* grad, double* F, double* J, double* T, int* iters,
+                      double* secs) -> int {
+    const int r = evaluate_w(mm, eps, grad, F, J, T, iters, secs, &ucur, &ucur, &acur);
+    if (r == WRI_OK) have_cur = true;
+    return r;
+  };
   double eps = o.eps0, F = 0, J = 0, T = 0, secs = 0;
   int iters = 0, rc;
   if ((rc = evaluate(m, eps, g, &F, &J, &T, &iters, &secs)) != WRI_OK) return rc;
@@ -484,7 +519,8 @@ int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sy
     hipLaunchKernelGGL(k_update, dim3(nbk), dim3(kRedThreads), 0, st, m_try, m, dir, n, scale, o.m_min, o.m_max);
     OUTER_HIP(hipGetLastError());
     double F1 = 0, J1 = 0, T1 = 0;
-    if ((rc = evaluate(m_try, eps, g_try, &F1, &J1, &T1, &iters, &secs)) != WRI_OK) return rc;
+    if ((rc = evaluate_w(m_try, eps, g_try, &F1, &J1, &T1, &iters, &secs, &utry, &ucur, &atry)) != WRI_OK)
+      return rc;
     const bool ok = F1 <= F;
     record(F1, J1, T1, eps, ok ? WRI_AWRI_ACCEPTED : WRI_AWRI_REJECTED, iters, secs);
     if (!ok) {
@@ -524,6 +560,10 @@ int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sy
     hipLaunchKernelGGL(k_copy32, dim3(nbk), dim3(kRedThreads), 0, st, m, m_try, n);
     OUTER_HIP(hipGetLastError());
     std::swap(g, g_try);
+    if (warm) {
+      std::swap(ucur, utry);
+      std::swap(acur, atry);
+    }
     F = F1; J = J1; T = T1;
     ++accepted;
   }

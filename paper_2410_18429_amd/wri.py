@@ -77,7 +77,7 @@ class WriAwriOptions(ctypes.Structure):
     _fields_ = [("gamma", c_double), ("eps_tv", c_double), ("eps0", c_double), ("eps_min", c_double),
                 ("step0", c_double), ("max_step", c_double), ("m_min", c_double), ("m_max", c_double),
                 ("max_outer", c_int32), ("memory", c_int32), ("max_iter", c_int32), ("flags", c_int32),
-                ("mask_sponge", c_int32), ("reserved_", c_int32)]
+                ("mask_sponge", c_int32), ("warm_start", c_int32)]
 
 
 class WriAwriRecord(ctypes.Structure):
@@ -381,7 +381,7 @@ def lbfgs_direction(g: torch.Tensor, S: torch.Tensor, Y: torch.Tensor, count: in
 
 def awri(batch: Batch, gamma=0.0, eps_tv=1e-9, eps0=1e-3, eps_min=1e-8, step0=0.01, max_step=0.0,
          m_min=0.0, m_max=0.0, max_outer=10, memory=5, max_iter=20000, flags=0, mask_sponge=True,
-         mode=None, history_cap=4096):
+         warm_start=False, mode=None, history_cap=4096):
     """Algorithm 2 on the batch's single grid.  The batch's model tensor is
     updated in place.  Returns (status code, list of evaluation records)."""
     if len(batch.grids_py) != 1:
@@ -389,8 +389,9 @@ def awri(batch: Batch, gamma=0.0, eps_tv=1e-9, eps0=1e-3, eps_min=1e-8, step0=0.
     mode = batch.mode if mode is None else mode
     o = WriAwriOptions(float(gamma), float(eps_tv), float(eps0), float(eps_min), float(step0), float(max_step),
                        float(m_min), float(m_max), int(max_outer), int(memory), int(max_iter), int(flags),
-                       int(bool(mask_sponge)), 0)
-    nbytes = lib().wri_awri_workspace_bytes(batch.cgrids, batch.csys, batch.nsys, mode, int(flags), int(memory))
+                       int(bool(mask_sponge)), int(bool(warm_start)))
+    qflags = int(flags) | (FLAG_WARM_START if warm_start else 0)
+    nbytes = lib().wri_awri_workspace_bytes(batch.cgrids, batch.csys, batch.nsys, mode, qflags, int(memory))
     if nbytes == 0:
         raise WriError(EINVAL, last_error())
     ws = torch.empty(nbytes, dtype=torch.uint8, device=batch.device)

@@ -185,6 +185,12 @@ def test_outer_loop_entry_points_validate_before_device_work():
     o.m_min, o.m_max = 0.0, 0.0
     need = L.wri_awri_workspace_bytes(gg, s, 1, wri.ESTIMATE, 0, 2)
     assert need > L.wri_workspace_bytes(gg, 1, s, 1, wri.ESTIMATE, 0) + 7 * 4 * 720
+    need_warm = L.wri_awri_workspace_bytes(gg, s, 1, wri.ESTIMATE, wri.FLAG_WARM_START, 2)
+    assert need_warm >= need + 2 * 8 * 720
+    o.warm_start = 1
+    assert L.wri_awri(gg, p, s, 1, wri.ESTIMATE, ctypes.byref(o), None, 0, ctypes.byref(n), p, need_warm - 1,
+                      None) == wri.ENOWS
+    o.warm_start = 0
     assert L.wri_awri(gg, p, s, 1, wri.ESTIMATE, ctypes.byref(o), None, 0, ctypes.byref(n), p, need - 1,
                       None) == wri.ENOWS
 

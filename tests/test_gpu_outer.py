@@ -147,3 +147,32 @@ def test_awri_adaptive_tolerance_schedule():
     assert all(b_ <= a_ for a_, b_ in zip(cur, cur[1:]))
     assert sum(r["kind"] == "accepted" for r in recs) == 6 or code == wri.NOT_CONVERGED
     assert all(r["iters"] > 0 for r in recs)
+
+
+def test_awri_warm_start_saves_iterations():
+    """The driver with warm starts: every solve after the first starts from the
+    current model's wavefields.  Same record structure as the cold run, fewer
+    CGLS iterations in the trials, and the final F equal to the oracle's
+    objective at the GPU's model (J is quadratic in the wavefield error, so the
+    looser error of a warm-started solve barely moves it)."""
+    _say("awri warm start")
+    p = _awri_problem()
+    g = p.grids[0]
+    bc = wri.Batch(p, device=DEV)
+    code_c, rc_ = wri.awri(bc, eps0=1e-6, eps_min=1e-7, max_outer=3, **AWRI_OPTS)
+    bw = wri.Batch(p, device=DEV)
+    code_w, rw_ = wri.awri(bw, eps0=1e-6, eps_min=1e-7, max_outer=3, warm_start=True, **AWRI_OPTS)
+    _say("  cold " + " ".join(f"{r['kind']}:{r['iters']}" for r in rc_))
+    _say("  warm " + " ".join(f"{r['kind']}:{r['iters']}" for r in rw_))
+    assert code_w in (wri.OK, wri.NOT_CONVERGED)
+    assert rw_[0]["iters"] == rc_[0]["iters"]          # the first solve is cold
+    trials_c = sum(r["iters"] for r in rc_[1:])
+    trials_w = sum(r["iters"] for r in rw_[1:])
+    _say(f"  CGLS iterations after the first evaluation: cold {trials_c}, warm {trials_w}")
+    assert trials_w < 0.8 * trials_c
+    mg = bw.m[0].cpu().numpy().astype(np.float64)
+    o = oracle.objective_grad(p, [mg.reshape(g.shape)], return_fields=False)
+    F_at = o["J"] + AWRI_OPTS["gamma"] * oracle.tv(g, mg, AWRI_OPTS["eps_tv"])
+    Flast = [r["F"] for r in rw_ if r["kind"] != "rejected"][-1]
+    _say(f"  final F warm {Flast:.10f}, oracle objective at that model {F_at:.10f}")
+    assert Flast == pytest.approx(F_at, rel=1e-4)
