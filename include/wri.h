@@ -249,7 +249,11 @@ typedef struct {
   int32_t flags;      /* solver flags (WRI_FLAG_*)                                          */
   int32_t mask_sponge;/* 1: the damping layer is not updated (gradient zeroed there)        */
   int32_t warm_start; /* 1: every solve after the first starts from the wavefields and
-                         source weights of the current model (WRI_FLAG_WARM_START)      */
+                         source weights of the current model (WRI_FLAG_WARM_START).
+                         Meant for a fixed tolerance (eps0 == eps_min): the value of a
+                         CGLS iterate only falls along the iteration, so a trial begun
+                         at the current wavefield passes the acceptance test almost
+                         regardless of the step and the tolerance is rarely halved    */
 } wri_awri_options;
 
 enum { WRI_AWRI_EVAL = 0, WRI_AWRI_ACCEPTED = 1, WRI_AWRI_REJECTED = 2 };
