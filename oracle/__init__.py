@@ -11,4 +11,5 @@ from .wri_oracle import (KNOWN, ESTIMATE, sponge, laplacian, helmholtz, restrict
                          unit_vector, system_operators, normal_matrix, factor, solve_known,
                          solve_estimate, objective_terms, gradient_term, objective_grad,
                          plain_helmholtz_solution, observed_data, apply_S, apply_SH,
-                         rhs_vector, normal_residual, cgls, paper_S_and_b, paper_f2)
+                         rhs_vector, normal_residual, cgls, paper_S_and_b, paper_f2, fwi_alpha,
+                         fwi_objective_grad, receiver_source_solution)

@@ -614,3 +614,66 @@ def awri(problem, m0, gamma: float, eps0: float, n_outer: int, memory: int = 5, 
         m, F, g = m_try, F_try, g_try
         accepted += 1
     return dict(m=m, history=history)
+
+
+# --------------------------------------------------------------------------
+# Reduced (conventional) FWI: eqs. FWI, PDEsolve, FWI2 — the baseline that WRI
+# is compared against.  Sparse direct solves; no iteration.
+# --------------------------------------------------------------------------
+
+def fwi_alpha(Pw: np.ndarray, d: np.ndarray) -> complex:
+    """Source weight minimising ||alpha P w - d||^2 for fixed w = A^{-1} e:
+    alpha = (P w)^H d / ||P w||^2 (0 when P w = 0)."""
+    den = float(np.vdot(Pw, Pw).real)
+    return complex(np.vdot(Pw, d) / den) if den > 0.0 else 0j
+
+
+def fwi_objective_grad(problem, m_list=None, mode=None, b_list=None) -> Dict:
+    """Reduced FWI objective and gradient (eq. FWI2 with the wavefield of eq.
+    PDEsolve):  f = 1/2 sum_ij ||alpha_ij P_i A_j^{-1} e_i - d_ij||^2.
+
+    KNOWN: alpha_ij = the system's given weight.  ESTIMATE: alpha_ij minimises
+    f for the current m (`fwi_alpha`, the minimisation over alpha that eq. FWI2
+    keeps), so the gradient below is that of the reduced function of m alone
+    (the alpha-derivative vanishes at the optimum).
+
+    Gradient by the adjoint-state method: with u = alpha A^{-1} e and
+    v = A^{-H} P^H (P u - d),  df/dm = -sum_ij omega_j^2 Re(conj(v) * u),
+    because dA/dm = omega^2 I (the sponge does not depend on m).
+
+    Returns dict(f, f_sys, g (list per grid, (nz, ny, nx)), alpha, u, v)."""
+    mode = mode or problem.mode
+    m_list = problem.m if m_list is None else m_list
+    grads = [np.zeros(g.n) for g in problem.grids]
+    ns = len(problem.systems)
+    f_sys, alphas, us, vs = np.zeros(ns), np.zeros(ns, complex), [None] * ns, [None] * ns
+    cache = {}
+    for k, s in enumerate(problem.systems):
+        g = problem.grids[s.grid]
+        key = (s.grid, s.freq)
+        if key not in cache:
+            b = None if b_list is None else b_list[s.grid]
+            A = helmholtz(g, m_list[s.grid], s.omega, b)
+            cache = {key: spl.splu(A.tocsc(), permc_spec="COLAMD")}
+        lu = cache[key]
+        P = restriction(g.n, s.rec)
+        d = np.asarray(s.d, dtype=np.complex128)
+        w = lu.solve(unit_vector(g.n, s.src))
+        alpha = complex(s.alpha) if mode == KNOWN else fwi_alpha(P @ w, d)
+        u = alpha * w
+        rho = P @ u - d
+        v = lu.solve(np.asarray(P.conj().T @ rho), trans="H")
+        f_sys[k] = 0.5 * float(np.vdot(rho, rho).real)
+        alphas[k] = alpha
+        grads[s.grid] += -(s.omega ** 2) * np.real(np.conj(v) * u)
+        us[k], vs[k] = u, v
+    return dict(f=float(f_sys.sum()), f_sys=f_sys, alpha=alphas, u=us, v=vs,
+                g=[gr.reshape(g.shape) for gr, g in zip(grads, problem.grids)])
+
+
+def receiver_source_solution(A, n: int, rec, values) -> np.ndarray:
+    """z = A^{-1} (P^H c): the wavefield of point sources of strengths c at the
+    receiver cells (the adjoint source of the reduced method, solved with A;
+    A is complex symmetric, so A^{-H} y = conj(A^{-1} conj(y)))."""
+    q = np.asarray(restriction(n, rec).conj().T @ np.asarray(values, dtype=np.complex128))
+    return spl.splu(A.tocsc(), permc_spec="COLAMD").solve(q)

@@ -4,6 +4,7 @@ force).  None of these re-types the oracle's own formula: each checks it
 through a different route, chosen so that a dropped term, a wrong sign, a
 conjugate-vs-transpose slip or a transposed operand fails at least one test.
 """
+import dataclasses
 import json
 import os
 
@@ -547,3 +548,113 @@ def test_awri_outer_loop_behaviour():
     for i, r in enumerate(h[:-1]):
         if not r["accepted"]:
             assert h[i + 1].get("reeval") and h[i + 1]["eps"] == pytest.approx(0.5 * r["eps"])
+
+
+# --------------------------------------------------------------------------
+# Reduced FWI baseline (eqs. FWI, PDEsolve, FWI2)
+# --------------------------------------------------------------------------
+
+def _fwi_problem(seed=31, mode=oracle.ESTIMATE):
+    p = wri_synth.custom_problem((9, 8, 7), nb=2, n_src=2, n_rec=7, seed=seed, freqs=(6.0, 9.0),
+                                 lam=0.0, mode=mode)
+    return p
+
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+def test_fwi_gradient_matches_central_differences(mode):
+    """Central differences of the reduced FWI objective (direct solves) at a
+    handful of cells, and a Taylor test: |f(m + t dm) - f(m) - t g.dm| = O(t^2).
+    A wrong sign, a missing conjugate or a dropped omega^2 in the adjoint-state
+    gradient fails it; in ESTIMATE mode so does a gradient that forgets that
+    alpha moves with m."""
+    p = _fwi_problem(mode=mode)
+    out = oracle.fwi_objective_grad(p)
+    g = out["g"][0].reshape(-1)
+    m = p.m[0].reshape(-1)
+    sh = p.grids[0].shape
+    rng = _rng(32)
+    cells = list(rng.choice(np.arange(m.size), 4, replace=False)) + [int(np.argmax(np.abs(g)))]
+    for c in cells:
+        step = 1e-4 * m[c]
+        mp, mm = m.copy(), m.copy()
+        mp[c] += step
+        mm[c] -= step
+        fd = (oracle.fwi_objective_grad(p, m_list=[mp.reshape(sh)])["f"] -
+              oracle.fwi_objective_grad(p, m_list=[mm.reshape(sh)])["f"]) / (2 * step)
+        assert abs(fd - g[c]) <= 1e-6 * np.abs(g).max(), (c, fd, g[c])
+    dm = rng.standard_normal(m.size) * m * 0.01
+    res = []
+    for t in (1.0, 0.5, 0.25):
+        ft = oracle.fwi_objective_grad(p, m_list=[(m + t * dm).reshape(sh)])["f"]
+        res.append(abs(ft - out["f"] - t * g @ dm))
+    assert 3.0 < res[0] / res[1] < 5.0 and 3.0 < res[1] / res[2] < 5.0
+
+
+def test_fwi_source_estimate_is_the_misfit_minimiser():
+    """ESTIMATE: the weight minimises 1/2 ||alpha P A^{-1} e - d||^2 (checked by
+    brute perturbation in four directions), and KNOWN with that weight gives the
+    same f and the same gradient (the alpha-derivative vanishes at the optimum)."""
+    p = _fwi_problem(seed=33)
+    est = oracle.fwi_objective_grad(p, mode=oracle.ESTIMATE)
+    for k, s in enumerate(p.systems):
+        A, P, e = oracle.system_operators(p, k)
+        Pw = P @ oracle.plain_helmholtz_solution(A, e)
+        f = lambda a: 0.5 * np.vdot(a * Pw - s.d, a * Pw - s.d).real
+        a0 = est["alpha"][k]
+        assert abs(f(a0) - est["f_sys"][k]) <= 1e-12 * f(a0)
+        for da in (1e-3, -1e-3, 1e-3j, -1e-3j):
+            assert f(a0 + da * abs(a0)) > f(a0)
+    pk = dataclasses.replace(p, mode=oracle.KNOWN, systems=[dataclasses.replace(s, alpha=complex(a))
+                                                            for s, a in zip(p.systems, est["alpha"])])
+    kn = oracle.fwi_objective_grad(pk)
+    assert abs(kn["f"] - est["f"]) <= 1e-12 * est["f"]
+    assert np.abs(kn["g"][0] - est["g"][0]).max() <= 1e-10 * np.abs(est["g"][0]).max()
+
+
+def test_fwi_is_the_small_lambda_limit_of_wri():
+    """With a known weight, the WRI objective and gradient (eqs. VarObj2,
+    VarG2, computed by the separate normal-equation route) divided by lam^2
+    tend to 2 f and 2 df/dm of reduced FWI as lam -> 0 (the PDE becomes a hard
+    constraint), with errors O(lam^2).  Pins the factor 1/2, the sign and the
+    adjoint field of the FWI gradient against an independent computation."""
+    p = _fwi_problem(seed=34, mode=oracle.KNOWN)
+    fwi = oracle.fwi_objective_grad(p)
+    ef, eg = [], []
+    for lam in (3e-4, 3e-5):   # smaller lam: the gradient's PDE residual drowns in cancellation
+        pl = dataclasses.replace(p, systems=[dataclasses.replace(s, lam=lam) for s in p.systems])
+        w = oracle.objective_grad(pl, mode=oracle.KNOWN)
+        ef.append(abs(w["J"] / lam ** 2 - 2.0 * fwi["f"]) / (2.0 * fwi["f"]))
+        eg.append(np.abs(w["g"][0] / lam ** 2 - 2.0 * fwi["g"][0]).max() / np.abs(2.0 * fwi["g"][0]).max())
+    assert ef[-1] < 1e-5 and eg[-1] < 1e-4, (ef, eg)
+    assert 30 < ef[0] / ef[1] < 300 and 30 < eg[0] / eg[1] < 300, (ef, eg)
+
+
+def test_fwi_zero_at_the_data_generating_model():
+    """Noise-free data from the same model: f = 0, g = 0 and, estimating the
+    weight, alpha = the true weight."""
+    p = wri_synth.custom_problem((10, 9, 8), nb=2, n_src=2, n_rec=8, seed=35, data="none", lam=0.0)
+    p.m_true = [m.copy() for m in p.m]
+    p = p.with_data(oracle.observed_data(p, noise=0.0))
+    out = oracle.fwi_objective_grad(p, mode=oracle.ESTIMATE)
+    for k, s in enumerate(p.systems):
+        assert abs(out["alpha"][k] - s.alpha) <= 1e-10 * abs(s.alpha)
+    dn = sum(np.vdot(s.d, s.d).real for s in p.systems)
+    assert out["f"] <= 1e-20 * dn
+    gref = np.abs(oracle.fwi_objective_grad(p, m_list=[m * 1.05 for m in p.m])["g"][0]).max()
+    assert np.abs(out["g"][0]).max() <= 1e-8 * gref
+
+
+def test_receiver_source_solution_is_adjoint_of_sampling():
+    """Reciprocity: for the complex-symmetric A, <P A^{-1} e_s, c> (plain
+    transpose) equals <e_s, A^{-1} P^T c>, i.e. the field of receiver sources
+    sampled at the source equals the source's field sampled at the receivers,
+    weighted by c."""
+    p = _fwi_problem(seed=36)
+    rng = _rng(37)
+    for k, s in enumerate(p.systems):
+        A, P, e = oracle.system_operators(p, k)
+        c = _crandn(rng, len(s.rec))
+        z = oracle.receiver_source_solution(A, p.grids[0].n, s.rec, c)
+        w = oracle.plain_helmholtz_solution(A, e)
+        lhs = np.sum(w[np.asarray(s.rec)] * c)
+        assert abs(z[s.src] - lhs) <= 1e-10 * abs(lhs)
