@@ -142,7 +142,7 @@ enum {
   WRI_FLAG_TIMING = 16,     /* launch the batched iterations eagerly with a HIP event
                                pair around every fused launch; totals via
                                wri_kernel_times() */
-  WRI_FLAG_WARM_START = 32  /* batched path only: u_out (required, one pointer per
+  WRI_FLAG_WARM_START = 32, /* batched path only: u_out (required, one pointer per
                                system) holds the initial wavefield on entry, and in
                                ESTIMATE mode sys[k].alpha the initial source weight.
                                CGLS starts from x0 = (u0, alpha0) with r0 = b - S x0;
@@ -150,6 +150,13 @@ enum {
                                zero-start residual), so the result meets the same
                                rtol as a cold start.  u0 = 0 reproduces the cold
                                start bit for bit. */
+  WRI_FLAG_ADJOINT_SOURCE = 64 /* WRI_KNOWN with lambda = 0 in every system: the
+                               right-hand side of the PDE rows is P^H d — point
+                               sources of strengths sys[k].d at the receiver cells —
+                               instead of alpha e (src and alpha are not used).  u then
+                               solves A u = P^H d; as A is complex symmetric,
+                               conj(u) solves A^H v = P^H conj(d), the adjoint field of
+                               reduced FWI (eqs. FWI, FWI2).  Not with WRI_FLAG_WARM_START. */
 };
 
 /* Workspace bytes needed by wri_solve / wri_objective_grad / estimate_source
@@ -287,6 +294,47 @@ size_t wri_awri_workspace_bytes(const wri_grid* grid, const wri_system* sys, int
 int wri_awri(const wri_grid* grid, float* m, const wri_system* sys, int32_t n_sys, int32_t mode,
              const wri_awri_options* opt, wri_awri_record* history, int32_t history_cap,
              int32_t* n_records, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Reduced (conventional) FWI baseline: eqs. FWI, PDEsolve, FWI2 --------
+ *
+ *     f = 1/2 sum_ij || alpha_ij P_i A_j^{-1} e_i - d_ij ||^2
+ *
+ * the objective WRI relaxes (section "3D Source free wavefield reconstruction
+ * inversion").  Per system: a forward solve A w = e (ESTIMATE) or
+ * A u = alpha e (KNOWN), both by the batched solver with lambda = 0; in
+ * ESTIMATE mode the weight that minimises the misfit for the current m,
+ * alpha = (P w)^H d / ||P w||^2 (0 when P w = 0), and u = alpha w (float64);
+ * the residual rho = P u - d; an adjoint solve A z = P^H conj(rho)
+ * (WRI_FLAG_ADJOINT_SOURCE; v = conj(z) solves A^H v = P^H rho); and
+ *     df/dm = - sum_ij omega_j^2 Re( conj(v) * u ) = - sum_ij omega_j^2 Re( z * u )
+ * (dA/dm = omega^2 I; with alpha at its optimum the alpha-derivative
+ * vanishes, so this is the gradient of the reduced function of m).
+ * Both solves stop at sys[k].rtol; sys[k].lambda is not used. */
+typedef struct {
+  double  f;              /* this system's 1/2 || alpha P u - d ||^2 (float64)   */
+  wri_c64 alpha;          /* KNOWN: the input weight; ESTIMATE: the estimate     */
+  int32_t iters_fwd, iters_adj;    /* CGLS iterations of the two solves         */
+  int32_t status_fwd, status_adj;  /* WRI_SYS_* of the two solves               */
+} wri_fwi_result;
+
+/* Workspace bytes of wri_fwi_objective_grad (host-only; 0 on invalid input):
+ * the solver's workspace plus two wavefields per system (w and z). */
+size_t wri_fwi_workspace_bytes(const wri_grid* grids, int32_t n_grids, const wri_system* sys, int32_t n_sys,
+                               int32_t mode, int32_t flags);
+/*   m[g]     DEVICE float32 n(g) per grid (host array of n_grids pointers)
+ *   flags    WRI_FLAG_PLAIN / NO_GRAPH / NO_AUTOTUNE / TIMING (not WARM_START)
+ *   f_out    HOST double: sum of the systems' f (required)
+ *   grad     host array of n_grids DEVICE float32 pointers receiving df/dm
+ *            (overwritten; zeros on grids without systems), or NULL
+ *   u_out    host array of n_sys DEVICE pointers receiving u = alpha w, or NULL
+ *   res      HOST, n_sys results (required when n_sys > 0)
+ * Returns WRI_OK, WRI_NOT_CONVERGED when a solve stopped at max_iter or
+ * diverged, WRI_EBREAKDOWN (results filled, gradient not computed), or the
+ * validation errors of wri_solve. */
+int wri_fwi_objective_grad(const wri_grid* grids, int32_t n_grids, const float* const* m, const wri_system* sys,
+                           int32_t n_sys, int32_t mode, int32_t max_iter, int32_t flags, double* f_out,
+                           float* const* grad, wri_c32* const* u_out, wri_fwi_result* res, void* ws,
+                           size_t ws_bytes, void* stream);
 
 /* Kernel time of the last WRI_FLAG_TIMING call on this thread (HIP event
  * pairs around every fused launch; one launch covers every active system).

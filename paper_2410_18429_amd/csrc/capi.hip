@@ -478,7 +478,7 @@ int launch_iteration(Ctx& C, int k, hipStream_t s) {
 }
 
 int launch_setup(Ctx& C) {
-  WRI_HIP(launch_init(C.dsys, C.dstate, C.n_sys, C.st));
+  WRI_HIP(launch_init(C.dsys, C.dstate, C.n_sys, C.st, 0, (C.flags & WRI_FLAG_ADJOINT_SOURCE) ? 1 : 0));
   WRI_HIP(launch_adj(cur_cfg(C), C.dsys, C.dstate, C.part_d, C.part_s, C.dgd, (int)C.hgd.size(), C.nblocks, C.st));
   return WRI_OK;
 }
@@ -808,7 +808,8 @@ int run_plain(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     const int n = S.nx * S.ny * S.nz;
     const bool est = C.mode == WRI_ESTIMATE;
     const double c = S.alpha_c;
-    WRI_HIP(launch_init(C.dsys + i, C.dstate + i, 1, C.st));  // x = 0, r1 = b1, r2 = lambda d
+    WRI_HIP(launch_init(C.dsys + i, C.dstate + i, 1, C.st, 0,   // x = 0, r1 = b1, r2 = lambda d
+                        (C.flags & WRI_FLAG_ADJOINT_SOURCE) ? 1 : 0));
     double sa_re = 0.0, sa_im = 0.0;
     // s = S^H r (wavefield rows on the device, source-weight row on the host)
     auto apply_SH = [&]() -> int {
@@ -899,6 +900,12 @@ int solve_common(const wri_grid* grids, int32_t n_grids, const float* const* m, 
     if (n_sys > 0 && u_out == nullptr) return fail(WRI_EINVAL, "WRI_FLAG_WARM_START needs u_out (the initial guess)");
     for (int i = 0; i < n_sys; ++i)
       if (u_out[i] == nullptr) return fail(WRI_EINVAL, "WRI_FLAG_WARM_START: u_out[%d] is NULL", i);
+  }
+  if (flags & WRI_FLAG_ADJOINT_SOURCE) {
+    if (mode != WRI_KNOWN) return fail(WRI_EINVAL, "WRI_FLAG_ADJOINT_SOURCE needs WRI_KNOWN");
+    if (flags & WRI_FLAG_WARM_START) return fail(WRI_EINVAL, "WRI_FLAG_ADJOINT_SOURCE with WRI_FLAG_WARM_START");
+    for (int i = 0; i < n_sys; ++i)
+      if (sys[i].lambda != 0.0) return fail(WRI_EINVAL, "WRI_FLAG_ADJOINT_SOURCE: system %d has lambda != 0", i);
   }
   Ctx C;
   C.grids = grids; C.n_grids = n_grids; C.m = m; C.sys = sys; C.n_sys = n_sys;

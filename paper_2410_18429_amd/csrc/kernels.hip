@@ -171,7 +171,7 @@ __device__ __forceinline__ double norm2d(float2 v) {
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, SysState* __restrict__ stv,
-                                              int warm) {
+                                              int warm, int rhs_rec) {
   const int rhs = blockIdx.y;
   const SysDev& S = sysv[rhs];
   const int n = S.nx * S.ny * S.nz;
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, S
     if (!warm) S.x[c] = z;
     S.p[0][c] = z;
     float2 r = z;
-    if (S.mode == 0 && c == S.src) r = f2((float)S.alpha.x, (float)S.alpha.y);
+    if (S.mode == 0 && !rhs_rec && c == S.src) r = f2((float)S.alpha.x, (float)S.alpha.y);
     S.r[1][c] = r;
   }
   if (blockIdx.x == 0) {
@@ -212,9 +212,22 @@ __global__ void __launch_bounds__(256) k_init(const SysDev* __restrict__ sysv, S
   }
 }
 
-hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s, int warm) {
+// Receiver sources: r1 = P^H d, the observed-data values placed at the
+// receiver cells (stream-ordered after k_init has zeroed r1; the cells of one
+// system are distinct).  grid = nsys blocks.
+__global__ void __launch_bounds__(256) k_rhs_at_receivers(const SysDev* __restrict__ sysv) {
+  const SysDev& S = sysv[blockIdx.x];
+  for (int q = threadIdx.x; q < S.n_rec; q += blockDim.x) S.r[1][S.rec[q]] = S.d[q];
+}
+
+hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s, int warm, int rhs_rec) {
   if (nsys <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init, dim3(256, nsys), dim3(256), 0, s, sys, st, warm);
+  hipLaunchKernelGGL(k_init, dim3(256, nsys), dim3(256), 0, s, sys, st, warm, rhs_rec);
+  if (rhs_rec) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rhs_at_receivers, dim3(nsys), dim3(256), 0, s, sys);
+  }
   return hipGetLastError();
 }
 

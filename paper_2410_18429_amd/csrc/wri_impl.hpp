@@ -99,7 +99,9 @@ struct GroupDesc {
 int report_error(int code, const char* fmt, ...);
 
 // ---- launchers (kernels.hip) -------------------------------------------
-hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s, int warm = 0);
+// rhs_rec = 1: the PDE rows' right-hand side is P^H d (receiver sources) instead
+// of alpha e (KNOWN mode with lambda = 0; the adjoint solve of reduced FWI).
+hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s, int warm = 0, int rhs_rec = 0);
 // Warm start, after a set-up adjoint pass on r = b: gamma0 = ||S^H b||^2 from the
 // pass's partials (nparts per system), then r = b - S x0 (x0 = 0 when b = 0).
 hipError_t launch_warm_residual(const SysDev* sys, SysState* st, const double* part_s, const int* nparts,

@@ -27,6 +27,7 @@ FLAG_NO_AUTOTUNE = 4
 FLAG_UNSCALED_ALPHA = 8
 FLAG_TIMING = 16
 FLAG_WARM_START = 32
+FLAG_ADJOINT_SOURCE = 64
 
 
 def alpha_scale(h: float) -> float:
@@ -88,6 +89,11 @@ class WriAwriRecord(ctypes.Structure):
 AWRI_KINDS = {0: "eval", 1: "accepted", 2: "rejected"}
 
 
+class WriFwiResult(ctypes.Structure):
+    _fields_ = [("f", c_double), ("alpha", WriC64), ("iters_fwd", c_int32), ("iters_adj", c_int32),
+                ("status_fwd", c_int32), ("status_adj", c_int32)]
+
+
 class WriError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"wri error {code}: {msg}")
@@ -146,6 +152,13 @@ def lib() -> ctypes.CDLL:
     L.wri_awri.argtypes = [POINTER(WriGrid), vp, POINTER(WriSystem), c_int32, c_int32, POINTER(WriAwriOptions),
                            POINTER(WriAwriRecord), c_int32, POINTER(c_int32), vp, c_size_t, vp]
     L.wri_awri.restype = c_int
+    L.wri_fwi_workspace_bytes.argtypes = [POINTER(WriGrid), c_int32, POINTER(WriSystem), c_int32, c_int32,
+                                          c_int32]
+    L.wri_fwi_workspace_bytes.restype = c_size_t
+    L.wri_fwi_objective_grad.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32, c_int32,
+                                         c_int32, c_int32, POINTER(c_double), pp, pp, POINTER(WriFwiResult), vp,
+                                         c_size_t, vp]
+    L.wri_fwi_objective_grad.restype = c_int
     _lib = L
     return L
 
@@ -153,7 +166,7 @@ def lib() -> ctypes.CDLL:
 EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_objective_grad", "estimate_source",
             "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version",
             "wri_tv_workspace_bytes", "wri_tv", "wri_lbfgs_workspace_bytes", "wri_lbfgs_direction",
-            "wri_awri_workspace_bytes", "wri_awri")
+            "wri_awri_workspace_bytes", "wri_awri", "wri_fwi_workspace_bytes", "wri_fwi_objective_grad")
 
 
 def kernel_times() -> dict:
@@ -241,6 +254,17 @@ class Batch:
             self._ws[key] = ws
         return ws
 
+    def fwi_workspace(self, mode, flags):
+        nbytes = lib().wri_fwi_workspace_bytes(self.cgrids, len(self.grids_py), self.csys, self.nsys, mode, flags)
+        if nbytes == 0:
+            raise WriError(EINVAL, last_error())
+        key = ("fwi", mode, flags & FLAG_PLAIN)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
     def grid_cells(self, g):
         gg = self.grids_py[g]
         return gg.nx * gg.ny * gg.nz
@@ -292,6 +316,32 @@ def objective_grad(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=None,
                                     _stream(batch.device))
     _check(code)
     return J.value, grads, _results(res, batch.nsys)
+
+
+def fwi_objective_grad(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=None, grad_out=None,
+                       with_grad=True):
+    """Reduced FWI baseline (eqs. FWI, PDEsolve, FWI2): f (float), per-grid
+    gradients (float32 device tensors, or None), per-system results
+    (f, alpha, iterations and statuses of the forward and adjoint solves)."""
+    mode = batch.mode if mode is None else mode
+    grads = None
+    gptr = None
+    if with_grad:
+        grads = grad_out or [torch.empty(batch.grid_cells(g), dtype=torch.float32, device=batch.device)
+                             for g in range(len(batch.grids_py))]
+        gptr = (c_void_p * max(1, len(grads)))(*[c_void_p(g.data_ptr()) for g in grads])
+    ws = batch.fwi_workspace(mode, flags)
+    res = (WriFwiResult * max(1, batch.nsys))()
+    f = c_double(0.0)
+    code = lib().wri_fwi_objective_grad(batch.cgrids, len(batch.grids_py), batch.m_ptrs(), batch.csys, batch.nsys,
+                                        mode, int(max_iter), int(flags), ctypes.byref(f), gptr,
+                                        _u_ptrs(batch, u_out), res, c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream(batch.device))
+    _check(code)
+    out = [dict(f=res[k].f, alpha=complex(res[k].alpha.re, res[k].alpha.im), iters_fwd=res[k].iters_fwd,
+                iters_adj=res[k].iters_adj, status_fwd=STATUS_NAMES.get(res[k].status_fwd, res[k].status_fwd),
+                status_adj=STATUS_NAMES.get(res[k].status_adj, res[k].status_adj)) for k in range(batch.nsys)]
+    return f.value, grads, out
 
 
 def estimate_source(batch: Batch, max_iter=20000, flags=0, u_out=None):

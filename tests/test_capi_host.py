@@ -50,6 +50,8 @@ def test_struct_layout_matches_header():
       printf("%zu %zu %zu %zu %zu %zu\n", sizeof(wri_awri_options), offsetof(wri_awri_options, max_outer),
              offsetof(wri_awri_options, mask_sponge), sizeof(wri_awri_record), offsetof(wri_awri_record, kind),
              offsetof(wri_awri_record, seconds));
+      printf("%zu %zu %zu %zu\n", sizeof(wri_fwi_result), offsetof(wri_fwi_result, alpha),
+             offsetof(wri_fwi_result, iters_adj), offsetof(wri_fwi_result, status_adj));
       return 0;
     }
     """
@@ -68,8 +70,10 @@ def test_struct_layout_matches_header():
     Tm = wri.WriTiming
     assert vals[15:19] == [ctypes.sizeof(Tm), Tm.fwd_ms_full.offset, Tm.adj_bytes_full.offset, Tm.tile_order.offset]
     O, Rr = wri.WriAwriOptions, wri.WriAwriRecord
-    assert vals[19:] == [ctypes.sizeof(O), O.max_outer.offset, O.mask_sponge.offset, ctypes.sizeof(Rr),
-                         Rr.kind.offset, Rr.seconds.offset]
+    assert vals[19:25] == [ctypes.sizeof(O), O.max_outer.offset, O.mask_sponge.offset, ctypes.sizeof(Rr),
+                           Rr.kind.offset, Rr.seconds.offset]
+    F = wri.WriFwiResult
+    assert vals[25:] == [ctypes.sizeof(F), F.alpha.offset, F.iters_adj.offset, F.status_adj.offset]
 
 
 def _mk(n_rec=4, dup=False, src=5, rec_bad=False, grid=0, lam=0.1, omega=30.0, rtol=1e-6, nb=2, v_ref=1500.0):
@@ -210,3 +214,53 @@ def test_warm_start_flag_validation():
     code = L.wri_solve(g, 1, m, s, 1, wri.ESTIMATE, 10, wri.FLAG_WARM_START | wri.FLAG_PLAIN, u, res, ws, 1 << 40,
                        None)
     assert code == wri.EINVAL and "batched" in wri.last_error()
+
+
+def test_adjoint_source_flag_validation():
+    """Receiver-source solves: KNOWN mode, lambda = 0, no warm start; rejected
+    before any device call."""
+    L = wri.lib()
+    res = (wri.WriResult * 1)()
+    m = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x2000))
+    ws = ctypes.c_void_p(0x3000)
+    g, s, rec = _mk(lam=0.0)
+    code = L.wri_solve(g, 1, m, s, 1, wri.ESTIMATE, 10, wri.FLAG_ADJOINT_SOURCE, None, res, ws, 1 << 40, None)
+    assert code == wri.EINVAL and "WRI_KNOWN" in wri.last_error()
+    u = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x4000))
+    code = L.wri_solve(g, 1, m, s, 1, wri.KNOWN, 10, wri.FLAG_ADJOINT_SOURCE | wri.FLAG_WARM_START, u, res, ws,
+                       1 << 40, None)
+    assert code == wri.EINVAL
+    g, s, rec = _mk(lam=0.1)
+    code = L.wri_solve(g, 1, m, s, 1, wri.KNOWN, 10, wri.FLAG_ADJOINT_SOURCE, None, res, ws, 1 << 40, None)
+    assert code == wri.EINVAL and "lambda" in wri.last_error()
+
+
+def test_fwi_entry_point_validates_before_device_work():
+    L = wri.lib()
+    g, s, rec = _mk(lam=0.3)   # lambda is not used by the FWI baseline
+    res = (wri.WriFwiResult * 1)()
+    m = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x2000))
+    f = ctypes.c_double(0.0)
+    need = L.wri_fwi_workspace_bytes(g, 1, s, 1, wri.ESTIMATE, 0)
+    solver = L.wri_workspace_bytes(g, 1, s, 1, wri.KNOWN, 0)
+    assert need > solver + 2 * 720 * 8
+    assert L.wri_fwi_workspace_bytes(g, 1, s, 1, 7, 0) == 0
+    code = L.wri_fwi_objective_grad(g, 1, m, s, 1, wri.ESTIMATE, 10, 0, f, None, None, res,
+                                    ctypes.c_void_p(0x3000), need - 1, None)
+    assert code == wri.ENOWS
+    code = L.wri_fwi_objective_grad(g, 1, m, s, 1, wri.ESTIMATE, 10, 0, None, None, None, res,
+                                    ctypes.c_void_p(0x3000), need, None)
+    assert code == wri.EINVAL and "f_out" in wri.last_error()
+    code = L.wri_fwi_objective_grad(g, 1, m, s, 1, wri.ESTIMATE, 10, wri.FLAG_WARM_START, f, None, None, res,
+                                    ctypes.c_void_p(0x3000), need, None)
+    assert code == wri.EINVAL
+    code = L.wri_fwi_objective_grad(g, 1, m, s, 1, wri.ESTIMATE, 10, wri.FLAG_ADJOINT_SOURCE, f, None, None, res,
+                                    ctypes.c_void_p(0x3000), need, None)
+    assert code == wri.EINVAL
+    gbad = (ctypes.c_void_p * 1)(None)
+    code = L.wri_fwi_objective_grad(g, 1, m, s, 1, wri.ESTIMATE, 10, 0, f, gbad, None, res,
+                                    ctypes.c_void_p(0x3000), need, None)
+    assert code == wri.EINVAL and "grad" in wri.last_error()
+    g2, s2, _ = _mk(dup=True)
+    assert L.wri_fwi_objective_grad(g2, 1, m, s2, 1, wri.ESTIMATE, 10, 0, f, None, None, res,
+                                    ctypes.c_void_p(0x3000), need, None) == wri.EDUP

@@ -1,0 +1,139 @@
+"""GPU parity of the reduced FWI baseline (eqs. FWI, PDEsolve, FWI2) and of
+the receiver-source solve it is built on, through the C ABI, against the CPU
+oracle (sparse direct solves, complex128).
+
+Tolerances: wavefields rel 1e-4, objective and source weight rel 1e-4,
+gradient 1e-3 of its max-norm (float32 wavefields, float64 reductions; both
+solves at rtol 1e-8).
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import wri_synth
+from paper_2410_18429_amd import wri
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+RTOL = 1e-8
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.init()
+    yield
+    torch.cuda.synchronize()
+
+
+# Geometry: the cross-sections must be wider than half a wavelength, or the
+# waves are evanescent between the sponges and the far receivers see signals at
+# the float32 floor of the solve (66 x 16 x 12 cells is below cut-off at 6 Hz).
+def _fwi_problem(shape=(66, 16, 12), mode="estimate", seed=51, freqs=(15.0, 20.0), n_src=2, n_rec=10, nb=2):
+    p = wri_synth.custom_problem(shape, nb=nb, n_src=n_src, n_rec=n_rec, seed=seed, freqs=freqs, rtol=RTOL,
+                                 mode=mode, lam=0.0)
+    # data from the true model (the problem's m is the start model)
+    p2 = dataclasses.replace(p, systems=[dataclasses.replace(s, alpha=wri_synth.alpha_true(s.freq))
+                                         for s in p.systems])
+    return p.with_data(oracle.observed_data(p2, noise=0.01))
+
+
+@pytest.mark.parametrize("plain", [0, 1])
+def test_receiver_source_solve_matches_oracle(plain):
+    """WRI_FLAG_ADJOINT_SOURCE: u = A^{-1} P^H d with d as point strengths at
+    the receivers, on a grid of two 64-wide tiles in x with a ragged tail."""
+    _say(f"receiver-source solve plain={plain}")
+    p = wri_synth.custom_problem((66, 16, 12), nb=2, n_src=2, n_rec=10, seed=52, freqs=(15.0, 20.0), rtol=RTOL,
+                                 mode="known", lam=0.0)
+    rng = np.random.default_rng(53)
+    p = p.with_data([rng.standard_normal(len(s.rec)) + 1j * rng.standard_normal(len(s.rec)) for s in p.systems])
+    flags = wri.FLAG_ADJOINT_SOURCE | (wri.FLAG_PLAIN if plain else 0)
+    u, res = wri.solve(wri.Batch(p, device=DEV, mode="known"), flags=flags)
+    for k, s in enumerate(p.systems):
+        A, P, e = oracle.system_operators(p, k)
+        ref = oracle.receiver_source_solution(A, p.grids[0].n, s.rec, s.d)
+        assert res[k]["status"] == "converged", res[k]
+        assert rel(_np(u[k]), ref) < 1e-4, (k, rel(_np(u[k]), ref))
+
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+def test_fwi_objective_grad_matches_oracle(mode):
+    _say(f"fwi objective/gradient mode={mode}")
+    p = _fwi_problem(mode=mode)
+    ref = oracle.fwi_objective_grad(p, mode=mode)
+    b = wri.Batch(p, device=DEV, mode=mode)
+    u = wri.alloc_wavefields(b)
+    f, grads, res = wri.fwi_objective_grad(b, u_out=u)
+    for k in range(len(p.systems)):
+        assert res[k]["status_fwd"] == "converged" and res[k]["status_adj"] == "converged", res[k]
+        assert abs(res[k]["alpha"] - ref["alpha"][k]) <= 1e-4 * abs(ref["alpha"][k])
+        assert abs(res[k]["f"] - ref["f_sys"][k]) <= 1e-4 * ref["f_sys"][k]
+        assert rel(_np(u[k]), ref["u"][k]) < 1e-4
+    assert abs(f - ref["f"]) <= 1e-4 * ref["f"]
+    g = grads[0].cpu().numpy().astype(np.float64).reshape(p.grids[0].shape)
+    gr = ref["g"][0]
+    err = np.abs(g - gr).max() / np.abs(gr).max()
+    assert err <= 1e-3, err
+
+
+def test_fwi_two_grids_empty_grid_and_no_receivers():
+    """Systems on two grids plus a grid with none (gradient zeros there); a
+    system without receivers contributes f = 0 and nothing to the gradient
+    (its adjoint right-hand side is zero)."""
+    _say("fwi two grids")
+    pa = _fwi_problem(shape=(33, 20, 14), seed=54, freqs=(12.0,))
+    pb = _fwi_problem(shape=(18, 25, 21), seed=55, freqs=(8.0,), nb=3)
+    ge = wri_synth.Grid(9, 8, 7, 10.0, 2, 1500.0)
+    sb = [dataclasses.replace(s, grid=1) for s in pb.systems]
+    sb[1] = dataclasses.replace(sb[1], rec=np.zeros(0, np.int32), d=np.zeros(0, complex))
+    p = dataclasses.replace(pa, grids=[pa.grids[0], pb.grids[0], ge], m=[pa.m[0], pb.m[0], np.full(ge.shape, 3e-7)],
+                            m_true=[pa.m_true[0], pb.m_true[0], np.full(ge.shape, 3e-7)],
+                            systems=[sb[0], pa.systems[0], sb[1], pa.systems[1]])
+    ref = oracle.fwi_objective_grad(p)
+    f, grads, res = wri.fwi_objective_grad(wri.Batch(p, device=DEV))
+    assert abs(f - ref["f"]) <= 1e-4 * ref["f"]
+    assert res[2]["f"] == 0.0 and res[2]["status_adj"] == "zero_rhs" and res[2]["alpha"] == 0
+    for gi in (0, 1):
+        g = grads[gi].cpu().numpy().astype(np.float64).reshape(p.grids[gi].shape)
+        assert np.abs(g - ref["g"][gi]).max() <= 1e-3 * np.abs(ref["g"][gi]).max(), gi
+    assert torch.count_nonzero(grads[2]).item() == 0
+
+
+def test_fwi_zero_at_the_data_generating_model():
+    """Noise-free data from the evaluated model: f is at the float32 floor,
+    the estimated weight is the true one, and the gradient is tiny next to
+    the gradient at a perturbed model."""
+    _say("fwi zero residual")
+    p = wri_synth.custom_problem((33, 20, 14), nb=2, n_src=2, n_rec=10, seed=56, freqs=(12.0,), rtol=RTOL,
+                                 lam=0.0, data="none")
+    p.m_true = [m.copy() for m in p.m]
+    p = p.with_data(oracle.observed_data(p, noise=0.0))
+    b = wri.Batch(p, device=DEV)
+    f, grads, res = wri.fwi_objective_grad(b)
+    dn = sum(np.vdot(s.d, s.d).real for s in p.systems)
+    assert f <= 1e-8 * dn, (f, dn)
+    for k, s in enumerate(p.systems):
+        assert abs(res[k]["alpha"] - s.alpha) <= 1e-4 * abs(s.alpha)
+    b.set_m([torch.as_tensor(p.m[0] * 1.03, dtype=torch.float32)])
+    _, gp, _ = wri.fwi_objective_grad(b)
+    assert grads[0].abs().max().item() <= 1e-2 * gp[0].abs().max().item()
