@@ -178,6 +178,51 @@ def awri_bench(name, updates, dev):
                       "runs": out, "speedup_vs_tight": {r["run"]: round(base / r["seconds"], 3) for r in out}}))
 
 
+def fwi_bench(name, steps, dev):
+    """Reduced FWI (eqs. FWI, PDEsolve, FWI2) against WRI on one workload: time
+    and CGLS iterations per objective-and-gradient evaluation of all systems
+    at the workload's tolerance (FWI: a forward and an adjoint Helmholtz solve
+    per system; WRI: one augmented solve)."""
+    import torch
+    import wri_synth
+    from paper_2410_18429_amd import wri
+    prob = wri_synth.make_config(name, seed=0)
+    g = prob.grids[0]
+    batch = wri.Batch(prob, device=dev)
+    out = {}
+    for label, fn in (("fwi", lambda: wri.fwi_objective_grad(batch)), ("wri", lambda: wri.objective_grad(batch))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            val, grads, res = fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        if label == "fwi":
+            it_f = [r["iters_fwd"] for r in res]
+            it_a = [r["iters_adj"] for r in res]
+            st = sorted(set(r["status_fwd"] for r in res) | set(r["status_adj"] for r in res))
+            out[label] = {"seconds_per_eval": round(sec, 3), "f": val, "iters_fwd_mean": float(np.mean(it_f)),
+                          "iters_adj_mean": float(np.mean(it_a)), "iters_total": int(sum(it_f) + sum(it_a)),
+                          "status": st}
+        else:
+            it = [r["iters"] for r in res]
+            out[label] = {"seconds_per_eval": round(sec, 3), "J": val, "iters_mean": float(np.mean(it)),
+                          "iters_total": int(sum(it)), "status": sorted(set(r["status"] for r in res))}
+        print(f"[fwi] {label}: {sec:.3f} s per evaluation, {out[label]}", file=sys.stderr, flush=True)
+    wri.fwi_objective_grad(batch, flags=wri.FLAG_TIMING)
+    torch.cuda.synchronize()
+    kt = wri.kernel_times()
+    out["adjoint_solve_kernels"] = {
+        "fwd_gbs": round(kt["fwd_bytes"] / (kt["fwd_ms"] * 1e-3) / 1e9, 1),
+        "adj_gbs": round(kt["adj_bytes"] / (kt["adj_ms"] * 1e-3) / 1e9, 1)}
+    print(json.dumps({"metric": "objective-and-gradient evaluations: reduced FWI vs WRI",
+                      "workload": f"{name}: {g.nx}x{g.ny}x{g.nz}, {len(prob.systems)} systems, ESTIMATE, "
+                                  f"rtol {prob.systems[0].rtol:g}",
+                      "steps": steps, **out,
+                      "fwi_over_wri_time": round(out["fwi"]["seconds_per_eval"] / out["wri"]["seconds_per_eval"], 3)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +239,9 @@ def main():
                     help="outer-loop measurement instead of the headline: Algorithm 2 (adaptive tolerance, "
                          "l-BFGS, TV) against fixed-tolerance WRI on --config (default medium)")
     ap.add_argument("--awri-updates", type=int, default=20)
+    ap.add_argument("--fwi", action="store_true",
+                    help="reduced-FWI baseline measurement instead of the headline: objective-and-gradient "
+                         "evaluations of FWI and WRI on --config")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="counter calibration: copy a buffer of this many MiB three times and exit")
     args = ap.parse_args()
@@ -218,6 +266,9 @@ def main():
         return
     if args.awri:
         awri_bench("medium" if args.config == "differentiation" else args.config, args.awri_updates, dev)
+        return
+    if args.fwi:
+        fwi_bench(args.config, args.steps, dev)
         return
     prob = wri_synth.make_config(args.config, seed=0)
     g = prob.grids[0]
