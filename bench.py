@@ -45,14 +45,14 @@ BYTES_NOTE = {"fwd": "36, +24 on even iterations (x update of two steps)", "adj"
 # kernels.hip + capi.hip + wri_impl.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "bbc4a5dcd39b66ae",
+    "sources_sha256": "83d7564c413c753b",
     "tiles": {
-        "8,1,32,1,0": {"fwd_x": {"fetch_kib": 1954908.2, "write_kib": 2359507.2},
-                       "fwd": {"fetch_kib": 1110185.6, "write_kib": 1573024.5},
-                       "adj": {"fetch_kib": 1120698.1, "write_kib": 1573063.1}},
-        "4,2,32,1,0": {"fwd_x": {"fetch_kib": 2043901.1, "write_kib": 2359650.0},
-                       "fwd": {"fetch_kib": 1181281.7, "write_kib": 1573106.2},
-                       "adj": {"fetch_kib": 1153011.4, "write_kib": 1573160.2}},
+        "8,1,32,1,0": {"fwd_x": {"fetch_kib": 2018831.1, "write_kib": 2359557.8},
+                       "fwd": {"fetch_kib": 1199676.2, "write_kib": 1573088.8},
+                       "adj": {"fetch_kib": 1184600.7, "write_kib": 1573103.8}},
+        "4,2,32,1,0": {"fwd_x": {"fetch_kib": 2059242.8, "write_kib": 2359676.2},
+                       "fwd": {"fetch_kib": 1224766.8, "write_kib": 1573146.2},
+                       "adj": {"fetch_kib": 1246132.0, "write_kib": 1573207.5}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
