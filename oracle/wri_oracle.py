@@ -677,3 +677,46 @@ def receiver_source_solution(A, n: int, rec, values) -> np.ndarray:
     A is complex symmetric, so A^{-H} y = conj(A^{-1} conj(y)))."""
     q = np.asarray(restriction(n, rec).conj().T @ np.asarray(values, dtype=np.complex128))
     return spl.splu(A.tocsc(), permc_spec="COLAMD").solve(q)
+
+
+# --------------------------------------------------------------------------
+# One model grid tied to per-frequency simulation grids (trilinear resampling)
+# --------------------------------------------------------------------------
+
+def _axis_interp(n_model: int, h_model: float, n_grid: int, h_grid: float) -> sp.csr_matrix:
+    """1-D linear interpolation from model nodes a*h_model to simulation nodes
+    i*h_grid (common origin), clamped to the model's extent."""
+    rows, cols, vals = [], [], []
+    for i in range(n_grid):
+        if n_model == 1:
+            rows.append(i); cols.append(0); vals.append(1.0)
+            continue
+        xi = min(max(i * h_grid / h_model, 0.0), n_model - 1.0)
+        a = min(int(np.floor(xi)), n_model - 2)
+        t = xi - a
+        rows += [i, i]; cols += [a, a + 1]; vals += [1.0 - t, t]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n_grid, n_model))
+
+
+def resample_matrix(model_grid, grid) -> sp.csr_matrix:
+    """R: trilinear interpolation of a model on `model_grid` at the nodes of
+    `grid` (cell (i, j, k) at (i h, j h, k h) on both), as the Kronecker product
+    of the three axes in the x-fastest cell order."""
+    Rx = _axis_interp(model_grid.nx, model_grid.h, grid.nx, grid.h)
+    Ry = _axis_interp(model_grid.ny, model_grid.h, grid.ny, grid.h)
+    Rz = _axis_interp(model_grid.nz, model_grid.h, grid.nz, grid.h)
+    return sp.kron(Rz, sp.kron(Ry, Rx)).tocsr()
+
+
+def objective_grad_model(problem, model_grid, m_model, mode=None) -> Dict:
+    """J and dJ/dm_model when every simulation grid takes its model as
+    m_g = R_g m_model: J from `objective_grad` at those models and, by the
+    chain rule, g_model = sum_g R_g^T g_g."""
+    mm = np.asarray(m_model, dtype=np.float64).reshape(-1)
+    Rs = [resample_matrix(model_grid, g) for g in problem.grids]
+    m_list = [(R @ mm).reshape(g.shape) for R, g in zip(Rs, problem.grids)]
+    out = objective_grad(problem, m_list=m_list, mode=mode, return_fields=False)
+    g = np.zeros(mm.size)
+    for R, gg in zip(Rs, out["g"]):
+        g += R.T @ gg.reshape(-1)
+    return dict(J=out["J"], g=g.reshape(model_grid.shape), m_list=m_list, alpha=out["alpha"])

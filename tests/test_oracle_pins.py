@@ -658,3 +658,60 @@ def test_receiver_source_solution_is_adjoint_of_sampling():
         w = oracle.plain_helmholtz_solution(A, e)
         lhs = np.sum(w[np.asarray(s.rec)] * c)
         assert abs(z[s.src] - lhs) <= 1e-10 * abs(lhs)
+
+
+# --------------------------------------------------------------------------
+# One model grid, per-frequency simulation grids (trilinear resampling)
+# --------------------------------------------------------------------------
+
+def test_resample_matches_scipy_linear_interpolation():
+    """R m equals scipy's RegularGridInterpolator (method 'linear') at the
+    simulation nodes, for grids coarser and finer than the model grid."""
+    from scipy.interpolate import RegularGridInterpolator
+    rng = _rng(61)
+    mg = Grid(9, 7, 6, 10.0, 0, 1500.0)
+    m = rng.standard_normal(mg.shape)
+    axes_m = [np.arange(n) * mg.h for n in mg.shape]  # (z, y, x)
+    f = RegularGridInterpolator(axes_m, m, method="linear")
+    for g in (Grid(5, 4, 3, 20.0, 0, 1500.0), Grid(13, 10, 8, 6.5, 0, 1500.0), Grid(9, 7, 6, 10.0, 0, 1500.0)):
+        zz, yy, xx = np.meshgrid(*[np.arange(n) * g.h for n in g.shape], indexing="ij")
+        ref = f(np.stack([zz.ravel(), yy.ravel(), xx.ravel()], axis=1))
+        out = oracle.resample_matrix(mg, g) @ m.reshape(-1)
+        assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_resample_affine_exact_and_partition_of_unity():
+    mg = Grid(8, 9, 10, 12.0, 0, 1500.0)
+    g = Grid(11, 13, 15, 7.7, 0, 1500.0)
+    R = oracle.resample_matrix(mg, g)
+    assert np.allclose(R @ np.ones(mg.n), 1.0, atol=1e-14, rtol=0)
+    assert R.data.min() >= 0.0
+    z, y, x = np.meshgrid(*[np.arange(n) * mg.h for n in mg.shape], indexing="ij")
+    aff = lambda x, y, z: 0.3 + 2e-3 * x - 1e-3 * y + 4e-3 * z
+    zg, yg, xg = np.meshgrid(*[np.arange(n) * g.h for n in g.shape], indexing="ij")
+    assert np.abs(R @ aff(x, y, z).ravel() - aff(xg, yg, zg).ravel()).max() < 1e-13
+    assert abs((oracle.resample_matrix(mg, mg) - sp.identity(mg.n)).max()) < 1e-15
+
+
+def test_objective_on_the_model_grid_gradient_matches_central_differences():
+    """Two simulation grids (different cell sizes) tied to one model grid:
+    dJ/dm_model from sum_g R_g^T g_g agrees with central differences of
+    J(R_g m_model) — pins the transpose in the chain rule."""
+    mgrid = Grid(8, 7, 6, 10.0, 0, 1500.0)
+    rng = _rng(62)
+    m_model = (1.0 / rng.uniform(1800.0, 2400.0, mgrid.shape) ** 2)
+    pa = wri_synth.custom_problem((8, 7, 6), h=10.0, nb=2, n_src=1, n_rec=5, seed=63, freqs=(9.0,), lam=0.03)
+    pb = wri_synth.custom_problem((5, 5, 4), h=17.0, nb=1, n_src=1, n_rec=4, seed=64, freqs=(6.0,), lam=0.03)
+    sb = [dataclasses.replace(s, grid=1) for s in pb.systems]
+    p = dataclasses.replace(pa, grids=[pa.grids[0], pb.grids[0]], m=[pa.m[0], pb.m[0]],
+                            m_true=[pa.m_true[0], pb.m_true[0]], systems=list(pa.systems) + sb)
+    out = oracle.objective_grad_model(p, mgrid, m_model)
+    g = out["g"].reshape(-1)
+    mm = m_model.reshape(-1)
+    for c in list(rng.choice(np.arange(mm.size), 4, replace=False)) + [int(np.argmax(np.abs(g)))]:
+        step = 1e-4 * mm[c]
+        mp, mn = mm.copy(), mm.copy()
+        mp[c] += step
+        mn[c] -= step
+        fd = (oracle.objective_grad_model(p, mgrid, mp)["J"] - oracle.objective_grad_model(p, mgrid, mn)["J"]) / (2 * step)
+        assert abs(fd - g[c]) <= 1e-6 * np.abs(g).max(), (c, fd, g[c])
