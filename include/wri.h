@@ -336,6 +336,45 @@ int wri_fwi_objective_grad(const wri_grid* grids, int32_t n_grids, const float* 
                            float* const* grad, wri_c32* const* u_out, wri_fwi_result* res, void* ws,
                            size_t ws_bytes, void* stream);
 
+/* ---- One model grid, per-frequency simulation grids --------------------
+ *
+ * Each frequency may be simulated on its own grid (a fixed number of points
+ * per wavelength, as in the grouping of systems by frequency, eq. Mmatrix2)
+ * while the inversion updates one model m on a model grid.  Every grid has
+ * its cell (i, j, k) at (i h, j h, k h) — a common origin at cell 0 — and the
+ * model grid must cover each simulation grid ((n_g - 1) h_g <= (n_m - 1) h_m
+ * per axis) and be at most 6.5x coarser than it.  The map R_g from the
+ * model grid to grid g is trilinear interpolation: per axis
+ * xi = clamp(i h_g / h_m, 0, n_m - 1), i0 = min(floor(xi), n_m - 2),
+ * weights (1 - t, t) on model cells (i0, i0 + 1), t = xi - i0 (an axis of one
+ * model cell has weight 1); the 3-D weight is the product.  Arithmetic in
+ * float64, values stored as float32.
+ *
+ * wri_model_to_grid:          m_grid = R_g m_model  (DEVICE float32 arrays)
+ * wri_grid_to_model_adjoint:  g_model = R_g^T g_grid, or += when accumulate != 0
+ *                             (a gather over model cells; deterministic)
+ * Both are stream-ordered and do not synchronise; WRI_EINVAL on bad grids. */
+int wri_model_to_grid(const wri_grid* model_grid, const float* m_model, const wri_grid* grid, float* m_grid,
+                      void* stream);
+int wri_grid_to_model_adjoint(const wri_grid* model_grid, const wri_grid* grid, const float* g_grid, float* g_model,
+                              int32_t accumulate, void* stream);
+
+/* Objective and gradient with the model on the model grid: m_g = R_g m_model
+ * for every simulation grid, the batched solve and gradient of
+ * wri_objective_grad on the simulation grids, then
+ *     grad_model = sum_g R_g^T grad_g
+ * (the chain rule through the interpolation).  grad_model: DEVICE float32 on
+ * the model grid (overwritten), or NULL for the objective only.  Other
+ * arguments and returns as wri_objective_grad; the workspace (from
+ * wri_model_workspace_bytes) adds m_g and grad_g of every simulation grid to
+ * the solver's. */
+size_t wri_model_workspace_bytes(const wri_grid* model_grid, const wri_grid* grids, int32_t n_grids,
+                                 const wri_system* sys, int32_t n_sys, int32_t mode, int32_t flags);
+int wri_objective_grad_model(const wri_grid* model_grid, const float* m_model, const wri_grid* grids,
+                             int32_t n_grids, const wri_system* sys, int32_t n_sys, int32_t mode, int32_t max_iter,
+                             int32_t flags, double* J_out, float* grad_model, wri_c32* const* u_out, wri_result* res,
+                             void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel time of the last WRI_FLAG_TIMING call on this thread (HIP event
  * pairs around every fused launch; one launch covers every active system).
  * Bytes are algorithmic: per cell, forward 36 B (+24 B for the x update on

@@ -159,6 +159,17 @@ def lib() -> ctypes.CDLL:
                                          c_int32, c_int32, POINTER(c_double), pp, pp, POINTER(WriFwiResult), vp,
                                          c_size_t, vp]
     L.wri_fwi_objective_grad.restype = c_int
+    L.wri_model_to_grid.argtypes = [POINTER(WriGrid), vp, POINTER(WriGrid), vp, vp]
+    L.wri_model_to_grid.restype = c_int
+    L.wri_grid_to_model_adjoint.argtypes = [POINTER(WriGrid), POINTER(WriGrid), vp, vp, c_int32, vp]
+    L.wri_grid_to_model_adjoint.restype = c_int
+    L.wri_model_workspace_bytes.argtypes = [POINTER(WriGrid), POINTER(WriGrid), c_int32, POINTER(WriSystem),
+                                            c_int32, c_int32, c_int32]
+    L.wri_model_workspace_bytes.restype = c_size_t
+    L.wri_objective_grad_model.argtypes = [POINTER(WriGrid), vp, POINTER(WriGrid), c_int32, POINTER(WriSystem),
+                                           c_int32, c_int32, c_int32, c_int32, POINTER(c_double), vp, pp,
+                                           POINTER(WriResult), vp, c_size_t, vp]
+    L.wri_objective_grad_model.restype = c_int
     _lib = L
     return L
 
@@ -166,7 +177,9 @@ def lib() -> ctypes.CDLL:
 EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_objective_grad", "estimate_source",
             "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version",
             "wri_tv_workspace_bytes", "wri_tv", "wri_lbfgs_workspace_bytes", "wri_lbfgs_direction",
-            "wri_awri_workspace_bytes", "wri_awri", "wri_fwi_workspace_bytes", "wri_fwi_objective_grad")
+            "wri_awri_workspace_bytes", "wri_awri", "wri_fwi_workspace_bytes", "wri_fwi_objective_grad",
+            "wri_model_to_grid", "wri_grid_to_model_adjoint", "wri_model_workspace_bytes",
+            "wri_objective_grad_model")
 
 
 def kernel_times() -> dict:
@@ -342,6 +355,62 @@ def fwi_objective_grad(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=N
                 iters_adj=res[k].iters_adj, status_fwd=STATUS_NAMES.get(res[k].status_fwd, res[k].status_fwd),
                 status_adj=STATUS_NAMES.get(res[k].status_adj, res[k].status_adj)) for k in range(batch.nsys)]
     return f.value, grads, out
+
+
+def model_to_grid(model_grid, m_model: torch.Tensor, grid, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Trilinear resampling of a model (float32 device tensor on model_grid)
+    onto `grid` (common origin at cell 0)."""
+    mg = make_grid(model_grid)
+    gg = make_grid(grid)
+    m_model = m_model.contiguous()
+    out = out if out is not None else torch.empty(grid.nx * grid.ny * grid.nz, dtype=torch.float32,
+                                                  device=m_model.device)
+    _check(lib().wri_model_to_grid(ctypes.byref(mg), c_void_p(m_model.data_ptr()), ctypes.byref(gg),
+                                   c_void_p(out.data_ptr()), _stream(m_model.device)))
+    return out
+
+
+def grid_to_model_adjoint(model_grid, grid, g_grid: torch.Tensor, out: Optional[torch.Tensor] = None,
+                          accumulate=False) -> torch.Tensor:
+    """Transpose of model_to_grid applied to g_grid (float32 device tensor on `grid`)."""
+    mg = make_grid(model_grid)
+    gg = make_grid(grid)
+    g_grid = g_grid.contiguous()
+    if out is None:
+        out = torch.empty(model_grid.nx * model_grid.ny * model_grid.nz, dtype=torch.float32, device=g_grid.device)
+    _check(lib().wri_grid_to_model_adjoint(ctypes.byref(mg), ctypes.byref(gg), c_void_p(g_grid.data_ptr()),
+                                           c_void_p(out.data_ptr()), int(bool(accumulate)), _stream(g_grid.device)))
+    return out
+
+
+def objective_grad_model(batch: Batch, model_grid, m_model: torch.Tensor, mode=None, max_iter=20000, flags=0,
+                         u_out=None, with_grad=True):
+    """J, dJ/dm on the model grid (float32 device tensor, or None), results:
+    every simulation grid of the batch takes its model by trilinear resampling
+    of m_model."""
+    mode = batch.mode if mode is None else mode
+    mg = make_grid(model_grid)
+    nbytes = lib().wri_model_workspace_bytes(ctypes.byref(mg), batch.cgrids, len(batch.grids_py), batch.csys,
+                                             batch.nsys, mode, flags)
+    if nbytes == 0:
+        raise WriError(EINVAL, last_error())
+    key = ("model", mode, flags & FLAG_PLAIN)
+    ws = batch._ws.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=batch.device)
+        batch._ws[key] = ws
+    m_model = m_model.to(batch.device, torch.float32).contiguous().reshape(-1)
+    grad = torch.empty_like(m_model) if with_grad else None
+    res = (WriResult * max(1, batch.nsys))()
+    J = c_double(0.0)
+    code = lib().wri_objective_grad_model(ctypes.byref(mg), c_void_p(m_model.data_ptr()), batch.cgrids,
+                                          len(batch.grids_py), batch.csys, batch.nsys, mode, int(max_iter),
+                                          int(flags), ctypes.byref(J),
+                                          c_void_p(grad.data_ptr()) if grad is not None else None,
+                                          _u_ptrs(batch, u_out), res, c_void_p(ws.data_ptr()), ws.numel(),
+                                          _stream(batch.device))
+    _check(code)
+    return J.value, grad, _results(res, batch.nsys)
 
 
 def estimate_source(batch: Batch, max_iter=20000, flags=0, u_out=None):

@@ -264,3 +264,29 @@ def test_fwi_entry_point_validates_before_device_work():
     g2, s2, _ = _mk(dup=True)
     assert L.wri_fwi_objective_grad(g2, 1, m, s2, 1, wri.ESTIMATE, 10, 0, f, None, None, res,
                                     ctypes.c_void_p(0x3000), need, None) == wri.EDUP
+
+
+def test_resampling_entry_points_validate_before_device_work():
+    L = wri.lib()
+    model = wri.WriGrid(10, 9, 8, 0, 10.0, 1500.0)
+    ok = wri.WriGrid(5, 4, 4, 0, 20.0, 1500.0)        # (n-1) h = 80, 60, 60 <= 90, 80, 70
+    beyond = wri.WriGrid(6, 4, 4, 0, 20.0, 1500.0)    # 100 > 90 along x
+    fine = wri.WriGrid(81, 72, 64, 0, 1.0, 1500.0)   # 10x finer than the model
+    p = ctypes.c_void_p(0x1000)
+    assert L.wri_model_to_grid(ctypes.byref(model), p, ctypes.byref(beyond), p, None) == wri.EINVAL
+    assert "beyond" in wri.last_error()
+    assert L.wri_model_to_grid(ctypes.byref(model), p, ctypes.byref(fine), p, None) == wri.EINVAL
+    assert "finer" in wri.last_error()
+    assert L.wri_model_to_grid(ctypes.byref(model), None, ctypes.byref(ok), p, None) == wri.EINVAL
+    assert L.wri_grid_to_model_adjoint(ctypes.byref(model), ctypes.byref(ok), p, None, 0, None) == wri.EINVAL
+    g, s, rec = _mk()
+    gg = (wri.WriGrid * 1)(wri.WriGrid(10, 9, 8, 2, 10.0, 1500.0))
+    need = L.wri_model_workspace_bytes(ctypes.byref(model), gg, 1, s, 1, wri.ESTIMATE, 0)
+    assert need > L.wri_workspace_bytes(gg, 1, s, 1, wri.ESTIMATE, 0) + 2 * 720 * 4
+    res = (wri.WriResult * 1)()
+    J = ctypes.c_double(0.0)
+    code = L.wri_objective_grad_model(ctypes.byref(model), p, gg, 1, s, 1, wri.ESTIMATE, 10, 0, J, p, None, res,
+                                      p, need - 1, None)
+    assert code == wri.ENOWS
+    gb = (wri.WriGrid * 1)(wri.WriGrid(11, 9, 8, 2, 10.0, 1500.0))   # beyond the model grid
+    assert L.wri_model_workspace_bytes(ctypes.byref(model), gb, 1, s, 1, wri.ESTIMATE, 0) == 0
