@@ -223,6 +223,64 @@ def fwi_bench(name, steps, dev):
                       "fwi_over_wri_time": round(out["fwi"]["seconds_per_eval"] / out["wri"]["seconds_per_eval"], 3)}))
 
 
+def model_grid_bench(steps, dev):
+    """The uneven workload (48^3, 64^3, 96^3 simulation grids at 8 points per
+    wavelength for 5/8/12 Hz) with one model grid that covers all three: time
+    of an objective-and-gradient evaluation with the model on the model grid
+    against the same evaluation with per-grid models, and the resampling
+    kernels on their own (HIP events on the current stream)."""
+    import torch
+    import wri_synth
+    from wri_synth import Grid
+    from paper_2410_18429_amd import wri
+    prob = wri_synth.make_config("uneven", seed=0)
+    h_m = 12.0
+    ext = [max((getattr(g, a) - 1) * g.h for g in prob.grids) for a in ("nx", "ny", "nz")]
+    mgrid = Grid(*[int(np.ceil(e / h_m)) + 1 for e in ext], h=h_m, nb=0, v_ref=1500.0)
+    batch = wri.Batch(prob, device=dev)
+    m_model = torch.full((mgrid.n,), 1.0 / 2000.0 ** 2, dtype=torch.float32, device=dev)
+    batch.set_m([wri.model_to_grid(mgrid, m_model, g) for g in prob.grids])
+    out = {}
+    for label, fn in (("model_grid", lambda: wri.objective_grad_model(batch, mgrid, m_model)),
+                      ("per_grid", lambda: wri.objective_grad(batch))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            J, _, res = fn()
+        torch.cuda.synchronize()
+        out[label] = {"seconds_per_eval": round((time.perf_counter() - t0) / steps, 4), "J": J,
+                      "iters_total": int(sum(r["iters"] for r in res))}
+        print(f"[model-grid] {label}: {out[label]}", file=sys.stderr, flush=True)
+    kern = []
+    gvec = [torch.randn(g.n, dtype=torch.float32, device=dev) for g in prob.grids]
+    gm = torch.empty(mgrid.n, dtype=torch.float32, device=dev)
+    reps = 20
+    for gi, g in enumerate(prob.grids):
+        mg = torch.empty(g.n, dtype=torch.float32, device=dev)
+        for name, fn, nbytes in (
+                ("model_to_grid", lambda: wri.model_to_grid(mgrid, m_model, g, out=mg), 4 * (mgrid.n + g.n)),
+                ("grid_to_model_adjoint", lambda: wri.grid_to_model_adjoint(mgrid, g, gvec[gi], out=gm),
+                 4 * (mgrid.n + g.n))):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            kern.append({"kernel": name, "grid": f"{g.nx}^3 h={g.h:g}", "ms": round(ms, 4),
+                         "algorithmic_bytes": nbytes, "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)})
+            print(f"[model-grid] {kern[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "objective-and-gradient evaluation with the model on one model grid",
+                      "workload": f"uneven: 96 systems on 48^3/64^3/96^3 grids; model grid "
+                                  f"{mgrid.nx}x{mgrid.ny}x{mgrid.nz} at {h_m:g} m",
+                      "steps": steps, **out, "resample_kernels": kern,
+                      "overhead": round(out["model_grid"]["seconds_per_eval"] / out["per_grid"]["seconds_per_eval"]
+                                        - 1.0, 4)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +297,9 @@ def main():
                     help="outer-loop measurement instead of the headline: Algorithm 2 (adaptive tolerance, "
                          "l-BFGS, TV) against fixed-tolerance WRI on --config (default medium)")
     ap.add_argument("--awri-updates", type=int, default=20)
+    ap.add_argument("--model-grid", action="store_true",
+                    help="model-grid measurement instead of the headline: the uneven workload with one model "
+                         "grid tied to its three simulation grids")
     ap.add_argument("--fwi", action="store_true",
                     help="reduced-FWI baseline measurement instead of the headline: objective-and-gradient "
                          "evaluations of FWI and WRI on --config")
@@ -269,6 +330,9 @@ def main():
         return
     if args.fwi:
         fwi_bench(args.config, args.steps, dev)
+        return
+    if args.model_grid:
+        model_grid_bench(args.steps, dev)
         return
     prob = wri_synth.make_config(args.config, seed=0)
     g = prob.grids[0]

@@ -106,25 +106,39 @@ __global__ void __launch_bounds__(kThreads) k_model_to_grid(Axis ax, Axis ay, Ax
   }
 }
 
-// g_model[M] (+)= sum over simulation cells c of weight(c, M) * g_grid[c]
+// g_model[M] (+)= sum over simulation cells c of weight(c, M) * g_grid[c].
+// One block per model row (b, d): the y and z lists are the same for the whole
+// row and live in LDS; each thread builds the x list of its own model cells.
+// Reads of g_grid along a list are contiguous across neighbouring threads.
 __global__ void __launch_bounds__(kThreads) k_grid_to_model(Axis ax, Axis ay, Axis az, const float* __restrict__ gg,
                                                             float* __restrict__ gm, int accumulate) {
-  const int64_t n = (int64_t)ax.n_m * ay.n_m * az.n_m;
+  __shared__ int sy[kMaxAxisList], sz[kMaxAxisList], cnt[2];
+  __shared__ double swy[kMaxAxisList], swz[kMaxAxisList];
   const int64_t pg = (int64_t)ax.n_g * ay.n_g;
-  for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < n; c += (int64_t)gridDim.x * kThreads) {
-    const int a = (int)(c % ax.n_m), b = (int)((c / ax.n_m) % ay.n_m), d = (int)(c / ((int64_t)ax.n_m * ay.n_m));
-    int ix[kMaxAxisList], iy[kMaxAxisList], iz[kMaxAxisList];
-    double wx[kMaxAxisList], wy[kMaxAxisList], wz[kMaxAxisList];
-    const int nx = axis_list(ax, a, ix, wx), ny = axis_list(ay, b, iy, wy), nz = axis_list(az, d, iz, wz);
+  const int64_t rows = (int64_t)ay.n_m * az.n_m;
+  for (int64_t rw = blockIdx.x; rw < rows; rw += gridDim.x) {
+  const int b = (int)(rw % ay.n_m), d = (int)(rw / ay.n_m);
+  __syncthreads();  // the previous row's lists are no longer read
+  if (threadIdx.x == 0) cnt[0] = axis_list(ay, b, sy, swy);
+  if (threadIdx.x == 64) cnt[1] = axis_list(az, d, sz, swz);
+  __syncthreads();
+  const int ny = cnt[0], nz = cnt[1];
+  const int64_t row_m = rw * ax.n_m;
+  for (int a = threadIdx.x; a < ax.n_m; a += kThreads) {
+    int ix[kMaxAxisList];
+    double wx[kMaxAxisList];
+    const int nx = axis_list(ax, a, ix, wx);
     double acc = 0.0;
     for (int r = 0; r < nz; ++r)
       for (int q = 0; q < ny; ++q) {
-        const int64_t row = (int64_t)iz[r] * pg + (int64_t)iy[q] * ax.n_g;
+        const int64_t row = (int64_t)sz[r] * pg + (int64_t)sy[q] * ax.n_g;
         double s = 0.0;
         for (int p = 0; p < nx; ++p) s += wx[p] * (double)gg[row + ix[p]];
-        acc += wz[r] * wy[q] * s;
+        acc += swz[r] * swy[q] * s;
       }
+    const int64_t c = row_m + a;
     gm[c] = accumulate ? (float)((double)gm[c] + acc) : (float)acc;
+  }
   }
 }
 
@@ -176,8 +190,9 @@ int grid_to_model(const wri_grid* model, const wri_grid* grid, const float* gg, 
   if (gg == nullptr || gm == nullptr) return report_error(WRI_EINVAL, "gradient pointer is NULL");
   Axis ax, ay, az;
   axes(model, grid, &ax, &ay, &az);
-  hipLaunchKernelGGL(k_grid_to_model, dim3(blocks_for((int64_t)model->nx * model->ny * model->nz)), dim3(kThreads),
-                     0, st, ax, ay, az, gg, gm, accumulate);
+  const int64_t rows = (int64_t)model->ny * model->nz;
+  hipLaunchKernelGGL(k_grid_to_model, dim3((unsigned)std::min<int64_t>(rows, 1 << 20)), dim3(kThreads), 0, st, ax, ay,
+                     az, gg, gm, accumulate);
   RS_HIP(hipGetLastError());
   return WRI_OK;
 }
