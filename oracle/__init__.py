@@ -13,4 +13,5 @@ from .wri_oracle import (KNOWN, ESTIMATE, sponge, laplacian, helmholtz, restrict
                          plain_helmholtz_solution, observed_data, apply_S, apply_SH,
                          rhs_vector, normal_residual, cgls, paper_S_and_b, paper_f2, fwi_alpha,
                          fwi_objective_grad, receiver_source_solution, resample_matrix,
-                         objective_grad_model)
+                         objective_grad_model, trilinear_point, offgrid_operators,
+                         solve_estimate_general, objective_grad_offgrid)

@@ -720,3 +720,101 @@ def objective_grad_model(problem, model_grid, m_model, mode=None) -> Dict:
     for R, gg in zip(Rs, out["g"]):
         g += R.T @ gg.reshape(-1)
     return dict(J=out["J"], g=g.reshape(model_grid.shape), m_list=m_list, alpha=out["alpha"])
+
+
+# --------------------------------------------------------------------------
+# Sources and receivers off the grid nodes (trilinear e and P)
+# --------------------------------------------------------------------------
+
+def trilinear_point(grid, xyz) -> Tuple[np.ndarray, np.ndarray]:
+    """Cells and weights of trilinear interpolation at the point xyz = (x, y, z)
+    [m], cell (i, j, k) at (i h, j h, k h), the point clamped into the grid.
+    Per axis xi = clamp(x / h, 0, n - 1), i0 = min(floor(xi), n - 2), weights
+    (1 - t, t) on (i0, i0 + 1); an axis of one cell has weight 1 on cell 0.
+    Returns the distinct cells (duplicates merged, zero weights dropped) and
+    their weights."""
+    per_axis = []
+    for coord, n in zip(xyz, (grid.nx, grid.ny, grid.nz)):
+        if n == 1:
+            per_axis.append([(0, 1.0)])
+            continue
+        xi = min(max(float(coord) / grid.h, 0.0), n - 1.0)
+        i0 = min(int(np.floor(xi)), n - 2)
+        t = xi - i0
+        per_axis.append([(i0, 1.0 - t), (i0 + 1, t)])
+    acc: Dict[int, float] = {}
+    for (k, wz) in per_axis[2]:
+        for (j, wy) in per_axis[1]:
+            for (i, wx) in per_axis[0]:
+                c = (k * grid.ny + j) * grid.nx + i
+                acc[c] = acc.get(c, 0.0) + wz * wy * wx
+    cells = np.array(sorted(c for c in acc if acc[c] != 0.0), dtype=np.int64)
+    return cells, np.array([acc[c] for c in cells])
+
+
+def offgrid_operators(grid, src_xyz, rec_xyz) -> Tuple[np.ndarray, sp.csr_matrix]:
+    """e (dense, the source spread over its cells) and P (n_rec x n, one
+    interpolation row per receiver)."""
+    e = np.zeros(grid.n, dtype=np.complex128)
+    cs, ws = trilinear_point(grid, src_xyz)
+    e[cs] = ws
+    rows, cols, vals = [], [], []
+    for q, r in enumerate(np.asarray(rec_xyz, dtype=np.float64).reshape(-1, 3)):
+        cr, wr = trilinear_point(grid, r)
+        rows += [q] * len(cr); cols += list(cr); vals += list(wr)
+    P = sp.csr_matrix((np.asarray(vals, dtype=np.complex128), (rows, cols)),
+                      shape=(len(np.asarray(rec_xyz).reshape(-1, 3)), grid.n))
+    return e, P
+
+
+def solve_estimate_general(A, P, lam, e, d, route="varpro") -> Tuple[np.ndarray, complex]:
+    """(u, alpha) = argmin ||A u - alpha e||^2 + lam^2 ||P u - d||^2 for a
+    general source vector e (eq. SimpObj with e spread over several cells).
+    route "varpro": u(alpha) = u0 + alpha u1 from the normal matrix, then the
+    scalar least-squares problem; route "augmented": the (n+1) normal system
+    of S = [[A, -e], [lam P, 0]]."""
+    n = A.shape[0]
+    PH = P.conj().T
+    if route == "augmented":
+        N = normal_matrix(A, P, lam)
+        c = (A.conj().T @ e).reshape(-1, 1)
+        r = (e.conj() @ A).reshape(1, -1)
+        K = sp.bmat([[N, sp.csc_matrix(-c)], [sp.csc_matrix(-r), sp.csc_matrix([[np.vdot(e, e)]])]]).tocsc()
+        x = factor(K).solve(np.concatenate([lam ** 2 * (PH @ d), [0.0]]))
+        return x[:n], complex(x[n])
+    lu = factor(normal_matrix(A, P, lam))
+    u0 = lu.solve(lam ** 2 * (PH @ d))
+    u1 = lu.solve(A.conj().T @ e)
+    a = np.concatenate([A @ u1 - e, lam * (P @ u1)])
+    c = np.concatenate([-(A @ u0), lam * (d - P @ u0)])
+    alpha = complex(np.vdot(a, c) / np.vdot(a, a))
+    return u0 + alpha * u1, alpha
+
+
+def objective_grad_offgrid(problem, src_xyz, rec_xyz, m_list=None, mode=None) -> Dict:
+    """Objective and gradient (eqs. VarObj2, VarG2) with off-grid sources and
+    receivers: system k uses e and P of `offgrid_operators` at src_xyz[k] and
+    rec_xyz[k] (its own rec and src cell indices are not used)."""
+    mode = mode or problem.mode
+    m_list = problem.m if m_list is None else m_list
+    grads = [np.zeros(g.n) for g in problem.grids]
+    ns = len(problem.systems)
+    Js, alphas, us = np.zeros(ns), np.zeros(ns, complex), [None] * ns
+    for k, s in enumerate(problem.systems):
+        g = problem.grids[s.grid]
+        A = helmholtz(g, m_list[s.grid], s.omega)
+        e, P = offgrid_operators(g, src_xyz[k], rec_xyz[k])
+        d = np.asarray(s.d, dtype=np.complex128)
+        if mode == KNOWN:
+            alpha = complex(s.alpha)
+            u = solve_known(A, P, s.lam, alpha, e, d)
+        else:
+            u, alpha = solve_estimate_general(A, P, s.lam, e, d)
+        r1 = A @ u - alpha * e
+        r2 = P @ u - d
+        Js[k] = float(np.vdot(r1, r1).real + s.lam ** 2 * np.vdot(r2, r2).real)
+        alphas[k] = alpha
+        grads[s.grid] += 2.0 * s.omega ** 2 * np.real(np.conj(u) * r1)
+        us[k] = u
+    return dict(J=float(Js.sum()), J_sys=Js, alpha=alphas, u=us,
+                g=[gr.reshape(g.shape) for gr, g in zip(grads, problem.grids)])

@@ -715,3 +715,90 @@ def test_objective_on_the_model_grid_gradient_matches_central_differences():
         mn[c] -= step
         fd = (oracle.objective_grad_model(p, mgrid, mp)["J"] - oracle.objective_grad_model(p, mgrid, mn)["J"]) / (2 * step)
         assert abs(fd - g[c]) <= 1e-6 * np.abs(g).max(), (c, fd, g[c])
+
+
+# --------------------------------------------------------------------------
+# Off-grid sources and receivers (trilinear e and P)
+# --------------------------------------------------------------------------
+
+def _offgrid_positions(p, rng, jitter=True):
+    """Source and receiver coordinates [m]: the problem's cells, moved by up to
+    half a cell when jitter is set; two receivers share a cell."""
+    g = p.grids[0]
+    def xyz(c):
+        c = int(c)
+        return np.array([c % g.nx, (c // g.nx) % g.ny, c // (g.nx * g.ny)], dtype=np.float64) * g.h
+    src, rec = [], []
+    for s in p.systems:
+        sp_ = xyz(s.src) + (rng.uniform(-0.5, 0.5, 3) * g.h if jitter else 0.0)
+        rr = np.array([xyz(c) for c in s.rec])
+        if jitter:
+            rr = rr + rng.uniform(-0.5, 0.5, rr.shape) * g.h
+            rr[1] = rr[0] + 0.3 * g.h   # within one cell of receiver 0
+        src.append(sp_)
+        rec.append(rr)
+    return src, rec
+
+
+def test_trilinear_point_matches_scipy_interpolation():
+    from scipy.interpolate import RegularGridInterpolator
+    rng = _rng(81)
+    g = Grid(7, 6, 5, 12.5, 0, 1500.0)
+    u = rng.standard_normal(g.shape)
+    f = RegularGridInterpolator([np.arange(n) * g.h for n in g.shape], u, method="linear")
+    for _ in range(50):
+        pt = rng.uniform(0, 1, 3) * np.array([(g.nx - 1), (g.ny - 1), (g.nz - 1)]) * g.h
+        cells, w = oracle.trilinear_point(g, pt)
+        assert abs(w.sum() - 1.0) < 1e-14 and len(set(cells)) == len(cells)
+        assert abs(np.dot(w, u.reshape(-1)[cells]) - f([pt[::-1]])[0]) < 1e-12
+    # a node gives one cell of weight one; a degenerate axis merges corners
+    cells, w = oracle.trilinear_point(g, np.array([2, 3, 1]) * g.h)
+    assert list(cells) == [(1 * g.ny + 3) * g.nx + 2] and np.allclose(w, [1.0])
+    g1 = Grid(7, 1, 5, 12.5, 0, 1500.0)
+    cells, w = oracle.trilinear_point(g1, (20.0, 0.0, 30.0))
+    assert len(cells) == 4 and abs(w.sum() - 1.0) < 1e-14
+
+
+def test_offgrid_at_nodes_equals_on_grid():
+    """Positions on the nodes: the off-grid objective, gradient, wavefields and
+    source weights equal the on-grid oracle's (independent e and P)."""
+    p = wri_synth.custom_problem((9, 8, 7), nb=2, n_src=2, n_rec=6, seed=82, lam=0.05)
+    src, rec = _offgrid_positions(p, _rng(83), jitter=False)
+    for mode in ("estimate", "known"):
+        a = oracle.objective_grad_offgrid(p, src, rec, mode=mode)
+        b = oracle.objective_grad(p, mode=mode)
+        assert abs(a["J"] - b["J"]) <= 1e-10 * b["J"]
+        assert np.abs(a["g"][0] - b["g"][0]).max() <= 1e-9 * np.abs(b["g"][0]).max()
+        for k in range(len(p.systems)):
+            assert abs(a["alpha"][k] - b["alpha"][k]) <= 1e-10 * abs(b["alpha"][k])
+
+
+def test_offgrid_estimate_routes_agree_and_alpha_stationary():
+    p = wri_synth.custom_problem((9, 8, 7), nb=2, n_src=1, n_rec=6, seed=84, lam=0.05)
+    src, rec = _offgrid_positions(p, _rng(85))
+    g = p.grids[0]
+    A = oracle.helmholtz(g, p.m[0], p.systems[0].omega)
+    e, P = oracle.offgrid_operators(g, src[0], rec[0])
+    d = p.systems[0].d
+    u1, a1 = oracle.solve_estimate_general(A, P, p.systems[0].lam, e, d, route="varpro")
+    u2, a2 = oracle.solve_estimate_general(A, P, p.systems[0].lam, e, d, route="augmented")
+    assert np.linalg.norm(u1 - u2) <= 1e-10 * np.linalg.norm(u2) and abs(a1 - a2) <= 1e-10 * abs(a2)
+    # at the optimum alpha = e^H A u / e^H e
+    assert abs(np.vdot(e, A @ u1) / np.vdot(e, e) - a1) <= 1e-10 * abs(a1)
+
+
+def test_offgrid_gradient_matches_central_differences():
+    p = wri_synth.custom_problem((9, 8, 7), nb=2, n_src=2, n_rec=6, seed=86, lam=0.05, freqs=(7.0,))
+    src, rec = _offgrid_positions(p, _rng(87))
+    out = oracle.objective_grad_offgrid(p, src, rec)
+    g = out["g"][0].reshape(-1)
+    m = p.m[0].reshape(-1)
+    rng = _rng(88)
+    for c in list(rng.choice(np.arange(m.size), 3, replace=False)) + [int(np.argmax(np.abs(g)))]:
+        step = 1e-4 * m[c]
+        mp, mn = m.copy(), m.copy()
+        mp[c] += step
+        mn[c] -= step
+        fd = (oracle.objective_grad_offgrid(p, src, rec, m_list=[mp.reshape(p.grids[0].shape)])["J"] -
+              oracle.objective_grad_offgrid(p, src, rec, m_list=[mn.reshape(p.grids[0].shape)])["J"]) / (2 * step)
+        assert abs(fd - g[c]) <= 1e-6 * np.abs(g).max(), (c, fd, g[c])
