@@ -375,6 +375,40 @@ int wri_objective_grad_model(const wri_grid* model_grid, const float* m_model, c
                              int32_t flags, double* J_out, float* grad_model, wri_c32* const* u_out, wri_result* res,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Sources and receivers off the grid nodes ---------------------------
+ *
+ * e and P of eq. ObjPen become trilinear interpolation at arbitrary points:
+ * a point (x, y, z) [m] (cell (i, j, k) at (i h, j h, k h)) is clamped into
+ * the grid and, per axis, xi = x / h, i0 = min(floor(xi), n - 2), weights
+ * (1 - t, t) on (i0, i0 + 1), t = xi - i0 (an axis of one cell: weight 1 on
+ * cell 0); the 3-D weights are products, duplicate cells merged and zero
+ * weights dropped.  e = sum_k w_k e_{c_k}; row q of P holds receiver q's
+ * weights.  Receivers may share cells.  In ESTIMATE mode the source column is
+ * -c e and the least-squares weight of the result is
+ * alpha_ls = e^H (A u) / e^H e.  The gradient keeps the form of eq. VarG2.
+ *
+ * The systems run one at a time on the library's single-operator stencil and
+ * vector kernels with host-driven float64 scalars, plus weighted source and
+ * receiver kernels (the fused batched kernels assume one cell per source and
+ * receiver). */
+typedef struct {
+  double        src[3];  /* source position (x, y, z) [m]                           */
+  const double* rec;     /* HOST, 3 * n_rec receiver positions (x, y, z) [m]        */
+} wri_positions;
+
+/* Workspace bytes (host-only; 0 on invalid input).  pos: n_sys entries. */
+size_t wri_offgrid_workspace_bytes(const wri_grid* grids, int32_t n_grids, const wri_system* sys, int32_t n_sys,
+                                   const wri_positions* pos);
+/* As wri_objective_grad, with sys[k].src and sys[k].rec replaced by pos[k]
+ * (sys[k].n_rec and sys[k].d still give the data).  grad may be NULL (a solve
+ * only).  flags: WRI_FLAG_UNSCALED_ALPHA; WRI_FLAG_WARM_START and
+ * WRI_FLAG_ADJOINT_SOURCE are rejected, the others have no effect.  Positions
+ * must be finite; points outside the grid are clamped onto its boundary. */
+int wri_objective_grad_offgrid(const wri_grid* grids, int32_t n_grids, const float* const* m, const wri_system* sys,
+                               int32_t n_sys, const wri_positions* pos, int32_t mode, int32_t max_iter,
+                               int32_t flags, double* J_out, float* const* grad, wri_c32* const* u_out,
+                               wri_result* res, void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel time of the last WRI_FLAG_TIMING call on this thread (HIP event
  * pairs around every fused launch; one launch covers every active system).
  * Bytes are algorithmic: per cell, forward 36 B (+24 B for the x update on

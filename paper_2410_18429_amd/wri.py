@@ -94,6 +94,10 @@ class WriFwiResult(ctypes.Structure):
                 ("status_fwd", c_int32), ("status_adj", c_int32)]
 
 
+class WriPositions(ctypes.Structure):
+    _fields_ = [("src", c_double * 3), ("rec", POINTER(c_double))]
+
+
 class WriError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"wri error {code}: {msg}")
@@ -170,6 +174,13 @@ def lib() -> ctypes.CDLL:
                                            c_int32, c_int32, c_int32, c_int32, POINTER(c_double), vp, pp,
                                            POINTER(WriResult), vp, c_size_t, vp]
     L.wri_objective_grad_model.restype = c_int
+    L.wri_offgrid_workspace_bytes.argtypes = [POINTER(WriGrid), c_int32, POINTER(WriSystem), c_int32,
+                                              POINTER(WriPositions)]
+    L.wri_offgrid_workspace_bytes.restype = c_size_t
+    L.wri_objective_grad_offgrid.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32,
+                                             POINTER(WriPositions), c_int32, c_int32, c_int32, POINTER(c_double), pp,
+                                             pp, POINTER(WriResult), vp, c_size_t, vp]
+    L.wri_objective_grad_offgrid.restype = c_int
     _lib = L
     return L
 
@@ -179,7 +190,7 @@ EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_objective_g
             "wri_tv_workspace_bytes", "wri_tv", "wri_lbfgs_workspace_bytes", "wri_lbfgs_direction",
             "wri_awri_workspace_bytes", "wri_awri", "wri_fwi_workspace_bytes", "wri_fwi_objective_grad",
             "wri_model_to_grid", "wri_grid_to_model_adjoint", "wri_model_workspace_bytes",
-            "wri_objective_grad_model")
+            "wri_objective_grad_model", "wri_offgrid_workspace_bytes", "wri_objective_grad_offgrid")
 
 
 def kernel_times() -> dict:
@@ -411,6 +422,44 @@ def objective_grad_model(batch: Batch, model_grid, m_model: torch.Tensor, mode=N
                                           _stream(batch.device))
     _check(code)
     return J.value, grad, _results(res, batch.nsys)
+
+
+def objective_grad_offgrid(batch: Batch, src_xyz, rec_xyz, mode=None, max_iter=20000, flags=0, u_out=None,
+                           with_grad=True):
+    """Objective, per-grid gradients (or None) and results with sources and
+    receivers at arbitrary points: src_xyz[k] (3 floats, metres) and rec_xyz[k]
+    (n_rec x 3) replace system k's source and receiver cells (trilinear
+    weights; cell (i, j, k) at (i h, j h, k h))."""
+    mode = batch.mode if mode is None else mode
+    recs = [np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(-1, 3)) for r in rec_xyz]
+    for k, r in enumerate(recs):
+        if r.shape[0] != batch.csys[k].n_rec:
+            raise ValueError(f"system {k}: {r.shape[0]} receiver positions for {batch.csys[k].n_rec} data")
+    pos = (WriPositions * max(1, batch.nsys))(
+        *[WriPositions((c_double * 3)(*[float(v) for v in src_xyz[k]]),
+                       recs[k].ctypes.data_as(POINTER(c_double)) if recs[k].size else None)
+          for k in range(batch.nsys)])
+    nbytes = lib().wri_offgrid_workspace_bytes(batch.cgrids, len(batch.grids_py), batch.csys, batch.nsys, pos)
+    if nbytes == 0:
+        raise WriError(EINVAL, last_error())
+    key = ("offgrid",)
+    ws = batch._ws.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=batch.device)
+        batch._ws[key] = ws
+    grads, gptr = None, None
+    if with_grad:
+        grads = [torch.empty(batch.grid_cells(g), dtype=torch.float32, device=batch.device)
+                 for g in range(len(batch.grids_py))]
+        gptr = (c_void_p * max(1, len(grads)))(*[c_void_p(g.data_ptr()) for g in grads])
+    res = (WriResult * max(1, batch.nsys))()
+    J = c_double(0.0)
+    code = lib().wri_objective_grad_offgrid(batch.cgrids, len(batch.grids_py), batch.m_ptrs(), batch.csys,
+                                            batch.nsys, pos, mode, int(max_iter), int(flags), ctypes.byref(J), gptr,
+                                            _u_ptrs(batch, u_out), res, c_void_p(ws.data_ptr()), ws.numel(),
+                                            _stream(batch.device))
+    _check(code)
+    return J.value, grads, _results(res, batch.nsys)
 
 
 def estimate_source(batch: Batch, max_iter=20000, flags=0, u_out=None):

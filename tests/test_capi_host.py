@@ -290,3 +290,27 @@ def test_resampling_entry_points_validate_before_device_work():
     assert code == wri.ENOWS
     gb = (wri.WriGrid * 1)(wri.WriGrid(11, 9, 8, 2, 10.0, 1500.0))   # beyond the model grid
     assert L.wri_model_workspace_bytes(ctypes.byref(model), gb, 1, s, 1, wri.ESTIMATE, 0) == 0
+
+
+def test_offgrid_entry_point_validates_before_device_work():
+    L = wri.lib()
+    g, s, rec = _mk()
+    rxyz = np.zeros((4, 3))
+    pos = (wri.WriPositions * 1)(wri.WriPositions((ctypes.c_double * 3)(5.0, 5.0, 5.0),
+                                                  rxyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    need = L.wri_offgrid_workspace_bytes(g, 1, s, 1, pos)
+    assert need > 5 * 720 * 8
+    res = (wri.WriResult * 1)()
+    m = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x2000))
+    J = ctypes.c_double(0.0)
+    ws = ctypes.c_void_p(0x3000)
+    assert L.wri_objective_grad_offgrid(g, 1, m, s, 1, pos, wri.ESTIMATE, 10, 0, J, None, None, res, ws, need - 1,
+                                        None) == wri.ENOWS
+    assert L.wri_objective_grad_offgrid(g, 1, m, s, 1, pos, wri.ESTIMATE, 10, wri.FLAG_WARM_START, J, None, None, res,
+                                        ws, need, None) == wri.EINVAL
+    rxyz[2, 1] = float("nan")
+    assert L.wri_offgrid_workspace_bytes(g, 1, s, 1, pos) == 0
+    assert L.wri_objective_grad_offgrid(g, 1, m, s, 1, pos, wri.ESTIMATE, 10, 0, J, None, None, res, ws, need,
+                                        None) == wri.EINVAL
+    assert "position" in wri.last_error()
+    assert ctypes.sizeof(wri.WriPositions) == 32
