@@ -346,7 +346,7 @@ def main():
                     help="counter calibration: copy a buffer of this many MiB three times and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the systems are independent: a batch would shard by system across GPUs).", file=sys.stderr)
         sys.exit(2)
 
