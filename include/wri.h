@@ -387,10 +387,10 @@ int wri_objective_grad_model(const wri_grid* model_grid, const float* m_model, c
  * -c e and the least-squares weight of the result is
  * alpha_ls = e^H (A u) / e^H e.  The gradient keeps the form of eq. VarG2.
  *
- * The systems run one at a time on the library's single-operator stencil and
- * vector kernels with host-driven float64 scalars, plus weighted source and
- * receiver kernels (the fused batched kernels assume one cell per source and
- * receiver). */
+ * All systems of a call iterate in lockstep on the library's single-operator
+ * stencil plus batched weighted source/receiver, vector and float64 reduction
+ * kernels, with the step scalars in device memory (the fused kernels assume
+ * one cell per source and receiver). */
 typedef struct {
   double        src[3];  /* source position (x, y, z) [m]                           */
   const double* rec;     /* HOST, 3 * n_rec receiver positions (x, y, z) [m]        */

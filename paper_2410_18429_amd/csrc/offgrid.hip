@@ -1,15 +1,18 @@
 // Sources and receivers off the grid nodes: the source vector e and the
 // receiver sampling P of eqs. ObjPen / SimpObj become trilinear interpolation
 // weights over up to 8 cells each, and the same CGLS (the reading of
-// Algorithm 1 used throughout the library) runs system by system with the
-// library's single-operator stencil and vector kernels plus the weighted
-// source and receiver kernels below.  Scalars are float64 on the host, every
-// reduction runs in one fixed order.
+// Algorithm 1 used throughout the library) runs for all systems of a call in
+// lockstep: the library's single-operator stencil for A and A^H, and batched
+// kernels (one block row per system) for the weighted source and receiver
+// terms, the vector updates and the float64 reductions.  Step scalars live in
+// device memory; the host checks the statuses every kCheck iterations and
+// stops launching the stencils of finished systems.
 //
 // P p: one thread per receiver sums its weighted cells (reads only).  P^H r2:
 // a gather over the distinct receiver cells of a system (each cell's list of
 // (receiver, weight) pairs is built on the host), so cells shared by several
 // receivers need no atomics.  Source cells are distinct by construction.
+// Every reduction runs in one fixed order.
 #include "../../include/wri.h"
 #include "wri_impl.hpp"
 
@@ -33,79 +36,292 @@ size_t al(size_t v) { return (v + kAl - 1) / kAl * kAl; }
 
 int nblk(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 4096)); }
 
-// r[cells] = alpha * w
-__global__ void k_og_src_set(float2* __restrict__ r, const int* __restrict__ cells, const double* __restrict__ w,
-                             int nc, double2 a) {
-  const int i = threadIdx.x;
-  if (i < nc) r[cells[i]] = make_float2((float)(a.x * w[i]), (float)(a.y * w[i]));
+constexpr int kParts = 128;  // partial sums per system and reduction
+constexpr int kCheck = 32;   // iterations between host checks of the statuses
+
+// One system, resident in the workspace.
+struct OgSys {
+  float2 *x, *r, *p, *s, *t, *r2, *t2;
+  const float2* d;
+  const int* scell; const double* sw;
+  const int* rptr; const int* rcell; const double* rw;
+  const int* uptr; const int* ucell; const int* uq; const double* uw;
+  int n, ns, nr, nu;
+  int est, max_iter, pad_[2];
+  double c, lam, rtol2, omega2;
+  double2 alpha;  // KNOWN-mode weight
+};
+
+// Mutable scalars of one system (float64).
+struct OgState {
+  double gamma, gamma0, a, beta, J;
+  double2 xa, pa, sa, eau;
+  int status, iters, pad_[2];
+};
+
+__device__ __forceinline__ double bsum(double v, double* red) {  // all threads get the block total
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < kThreads / 64; ++i) r += red[i];
+  __syncthreads();
+  return r;
 }
 
-// t[cells] -= cp * w
-__global__ void k_og_src_sub(float2* __restrict__ t, const int* __restrict__ cells, const double* __restrict__ w,
-                             int nc, double2 cp) {
-  const int i = threadIdx.x;
-  if (i < nc) {
-    const float2 v = t[cells[i]];
-    t[cells[i]] = make_float2((float)((double)v.x - cp.x * w[i]), (float)((double)v.y - cp.y * w[i]));
+__device__ __forceinline__ float2 f2d(double a, double b) { return make_float2((float)a, (float)b); }
+
+// x = 0, r = 0 (grid (blocks, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_zero(const OgSys* __restrict__ sy) {
+  const OgSys& S = sy[blockIdx.y];
+  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
+    S.x[c] = make_float2(0.f, 0.f);
+    S.r[c] = make_float2(0.f, 0.f);
   }
 }
 
-// out = sum_k w_k v[cells_k] (one thread, fixed order)
-__global__ void k_og_src_dot(const float2* __restrict__ v, const int* __restrict__ cells,
-                             const double* __restrict__ w, int nc, double2* __restrict__ out) {
-  if (threadIdx.x != 0) return;
-  double re = 0.0, im = 0.0;
-  for (int i = 0; i < nc; ++i) {
-    const float2 x = v[cells[i]];
-    re += w[i] * (double)x.x;
-    im += w[i] * (double)x.y;
+// r[src] = alpha e (KNOWN), r2 = lam d, state reset (grid nsys)
+__global__ void __launch_bounds__(kThreads) k_og_init(const OgSys* __restrict__ sy, OgState* __restrict__ stv) {
+  const OgSys& S = sy[blockIdx.x];
+  if (!S.est && (int)threadIdx.x < S.ns) {
+    const double w = S.sw[threadIdx.x];
+    S.r[S.scell[threadIdx.x]] = f2d(S.alpha.x * w, S.alpha.y * w);
   }
-  *out = make_double2(re, im);
+  for (int q = threadIdx.x; q < S.nr; q += kThreads)
+    S.r2[q] = f2d(S.lam * (double)S.d[q].x, S.lam * (double)S.d[q].y);
+  if (threadIdx.x == 0) {
+    OgState& T = stv[blockIdx.x];
+    T = OgState{};
+    T.status = kActive;
+  }
 }
 
-// t2[q] = lam * sum_j w_j p[cell_j] over receiver q's cells
-__global__ void k_og_gather(float2* __restrict__ t2, const float2* __restrict__ p, const int* __restrict__ ptr,
-                            const int* __restrict__ cell, const double* __restrict__ w, int n_rec, double lam) {
+// t[src] -= c pa w  (grid nsys)
+__global__ void __launch_bounds__(64) k_og_src_sub(const OgSys* __restrict__ sy, const OgState* __restrict__ stv) {
+  const OgSys& S = sy[blockIdx.x];
+  const OgState& T = stv[blockIdx.x];
+  if (T.status != kActive || !S.est || (int)threadIdx.x >= S.ns) return;
+  const int c = S.scell[threadIdx.x];
+  const double w = S.sw[threadIdx.x];
+  const float2 v = S.t[c];
+  S.t[c] = f2d((double)v.x - S.c * T.pa.x * w, (double)v.y - S.c * T.pa.y * w);
+}
+
+// t2 = lam P p  (grid (blocks, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_gather(const OgSys* __restrict__ sy,
+                                                        const OgState* __restrict__ stv) {
+  const OgSys& S = sy[blockIdx.y];
+  if (stv[blockIdx.y].status != kActive) return;
   const int q = blockIdx.x * kThreads + threadIdx.x;
-  if (q >= n_rec) return;
+  if (q >= S.nr) return;
   double re = 0.0, im = 0.0;
-  for (int j = ptr[q]; j < ptr[q + 1]; ++j) {
-    const float2 x = p[cell[j]];
-    re += w[j] * (double)x.x;
-    im += w[j] * (double)x.y;
+  for (int j = S.rptr[q]; j < S.rptr[q + 1]; ++j) {
+    const float2 v = S.p[S.rcell[j]];
+    re += S.rw[j] * (double)v.x;
+    im += S.rw[j] * (double)v.y;
   }
-  t2[q] = make_float2((float)(lam * re), (float)(lam * im));
+  S.t2[q] = f2d(S.lam * re, S.lam * im);
 }
 
-// s[ucell[u]] += lam * sum_j w_j r2[q_j] over the (receiver, weight) pairs of
-// distinct cell u
-__global__ void k_og_scatter(float2* __restrict__ s, const float2* __restrict__ r2, const int* __restrict__ ptr,
-                             const int* __restrict__ ucell, const int* __restrict__ uq, const double* __restrict__ uw,
-                             int n_u, double lam) {
+// s[u] += lam sum_j w_j r2[q_j] over the distinct receiver cells  (grid (blocks, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_scatter(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
+                                                         int all) {
+  const OgSys& S = sy[blockIdx.y];
+  if (!all && stv[blockIdx.y].status != kActive) return;
   const int u = blockIdx.x * kThreads + threadIdx.x;
-  if (u >= n_u) return;
+  if (u >= S.nu) return;
   double re = 0.0, im = 0.0;
-  for (int j = ptr[u]; j < ptr[u + 1]; ++j) {
-    const float2 x = r2[uq[j]];
-    re += uw[j] * (double)x.x;
-    im += uw[j] * (double)x.y;
+  for (int j = S.uptr[u]; j < S.uptr[u + 1]; ++j) {
+    const float2 v = S.r2[S.uq[j]];
+    re += S.uw[j] * (double)v.x;
+    im += S.uw[j] * (double)v.y;
   }
-  const float2 v = s[ucell[u]];
-  s[ucell[u]] = make_float2((float)((double)v.x + lam * re), (float)((double)v.y + lam * im));
+  const int c = S.ucell[u];
+  const float2 v = S.s[c];
+  S.s[c] = f2d((double)v.x + S.lam * re, (double)v.y + S.lam * im);
 }
 
-// r2 = lam * d
-__global__ void k_og_r2(float2* __restrict__ r2, const float2* __restrict__ d, int n, double lam) {
-  const int q = blockIdx.x * kThreads + threadIdx.x;
-  if (q < n) r2[q] = make_float2((float)(lam * (double)d[q].x), (float)(lam * (double)d[q].y));
+// per-system partial sums of |v|^2, v = t (which 0), s (1) or r (2)  (grid (kParts, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_norm(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
+                                                      int which, int all, double* __restrict__ parts) {
+  __shared__ double red[kThreads / 64];
+  const OgSys& S = sy[blockIdx.y];
+  const bool on = all || stv[blockIdx.y].status == kActive;  // uniform over the block
+  const float2* v = which == 0 ? S.t : (which == 1 ? S.s : S.r);
+  double acc = 0.0;
+  if (on)
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += kParts * kThreads) {
+      const float2 x = v[c];
+      acc += (double)x.x * x.x + (double)x.y * x.y;
+    }
+  acc = bsum(acc, red);
+  if (threadIdx.x == 0) parts[blockIdx.y * kParts + blockIdx.x] = acc;
 }
 
-// g += -2 omega^2 Re(conj(u) r1)  (r1 = alpha e - A u, the recurred PDE residual)
-__global__ void k_og_grad(float* __restrict__ g, const float2* __restrict__ u, const float2* __restrict__ r, int n,
-                          double w2) {
+// gamma0 = ||S^H b||^2 after the set-up pass: p_a = s_a, statuses  (grid nsys)
+__global__ void __launch_bounds__(kThreads) k_og_start(const OgSys* __restrict__ sy, OgState* __restrict__ stv,
+                                                       const double* __restrict__ parts) {
+  __shared__ double red[kThreads / 64];
+  const OgSys& S = sy[blockIdx.x];
+  OgState& T = stv[blockIdx.x];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
+  v = bsum(v, red);
+  double sr = 0.0, si = 0.0;
+  if (S.est)
+    for (int i = 0; i < S.ns; ++i) {
+      const float2 x = S.r[S.scell[i]];
+      sr -= S.c * S.sw[i] * (double)x.x;
+      si -= S.c * S.sw[i] * (double)x.y;
+    }
+  if (threadIdx.x == 0) {
+    const double g = v + sr * sr + si * si;
+    T.gamma = T.gamma0 = g;
+    T.sa = T.pa = make_double2(sr, si);
+    if (g == 0.0) T.status = kZeroRhs;
+    else if (g <= S.rtol2 * g) T.status = kConverged;
+    else if (S.max_iter <= 0) T.status = kMaxIter;
+  }
+}
+
+// p = s (grid (blocks, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_copy_ps(const OgSys* __restrict__ sy) {
+  const OgSys& S = sy[blockIdx.y];
+  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) S.p[c] = S.s[c];
+}
+
+// delta = ||t||^2 + ||t2||^2, a = gamma / delta, x_a += a p_a, r2 -= a t2  (grid nsys)
+__global__ void __launch_bounds__(kThreads) k_og_alpha(const OgSys* __restrict__ sy, OgState* __restrict__ stv,
+                                                       const double* __restrict__ parts) {
+  __shared__ double red[kThreads / 64];
+  const OgSys& S = sy[blockIdx.x];
+  OgState& T = stv[blockIdx.x];
+  if (T.status != kActive) return;  // uniform over the block
+  double v = 0.0;
+  for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
+  for (int q = threadIdx.x; q < S.nr; q += kThreads) {
+    const float2 x = S.t2[q];
+    v += (double)x.x * x.x + (double)x.y * x.y;
+  }
+  const double delta = bsum(v, red);
+  const double gamma = T.gamma;
+  const bool bad = !(delta > 0.0) || !isfinite(delta) || !isfinite(gamma);
+  const double a = bad ? 0.0 : gamma / delta;
+  if (!bad)
+    for (int q = threadIdx.x; q < S.nr; q += kThreads) {
+      const float2 r = S.r2[q], t = S.t2[q];
+      S.r2[q] = f2d((double)r.x - a * t.x, (double)r.y - a * t.y);
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (bad) {
+      T.status = kBreakdown;
+    } else {
+      T.a = a;
+      T.xa = make_double2(T.xa.x + a * T.pa.x, T.xa.y + a * T.pa.y);
+    }
+  }
+}
+
+// x += a p, r -= a t  (grid (blocks, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_update(const OgSys* __restrict__ sy,
+                                                        const OgState* __restrict__ stv) {
+  const OgSys& S = sy[blockIdx.y];
+  const OgState& T = stv[blockIdx.y];
+  if (T.status != kActive) return;
+  const double a = T.a;
+  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
+    const float2 x = S.x[c], p = S.p[c], r = S.r[c], t = S.t[c];
+    S.x[c] = f2d((double)x.x + a * p.x, (double)x.y + a * p.y);
+    S.r[c] = f2d((double)r.x - a * t.x, (double)r.y - a * t.y);
+  }
+}
+
+// s_a = -c e^H r, gamma' = ||s||^2 + |s_a|^2, beta, statuses, p_a  (grid nsys)
+__global__ void __launch_bounds__(kThreads) k_og_beta(const OgSys* __restrict__ sy, OgState* __restrict__ stv,
+                                                      const double* __restrict__ parts) {
+  __shared__ double red[kThreads / 64];
+  const OgSys& S = sy[blockIdx.x];
+  OgState& T = stv[blockIdx.x];
+  if (T.status != kActive) return;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
+  v = bsum(v, red);
+  if (threadIdx.x == 0) {
+    double sr = 0.0, si = 0.0;
+    if (S.est)
+      for (int i = 0; i < S.ns; ++i) {
+        const float2 x = S.r[S.scell[i]];
+        sr -= S.c * S.sw[i] * (double)x.x;
+        si -= S.c * S.sw[i] * (double)x.y;
+      }
+    const double gnew = v + sr * sr + si * si;
+    const double beta = gnew / T.gamma;
+    T.beta = beta;
+    T.gamma = gnew;
+    T.sa = make_double2(sr, si);
+    T.pa = make_double2(sr + beta * T.pa.x, si + beta * T.pa.y);
+    T.iters += 1;
+    if (gnew <= S.rtol2 * T.gamma0) T.status = kConverged;
+    else if (!isfinite(gnew)) T.status = kBreakdown;
+    else if (T.iters >= S.max_iter) T.status = kMaxIter;
+  }
+}
+
+// p = s + beta p  (grid (blocks, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_xpby(const OgSys* __restrict__ sy, const OgState* __restrict__ stv) {
+  const OgSys& S = sy[blockIdx.y];
+  const OgState& T = stv[blockIdx.y];
+  if (T.status != kActive) return;
+  const double b = T.beta;
+  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
+    const float2 s = S.s[c], p = S.p[c];
+    S.p[c] = f2d((double)s.x + b * p.x, (double)s.y + b * p.y);
+  }
+}
+
+// J = ||r||^2 + ||r2||^2; e^H (A u) from t = A x  (grid nsys)
+__global__ void __launch_bounds__(kThreads) k_og_final(const OgSys* __restrict__ sy, OgState* __restrict__ stv,
+                                                       const double* __restrict__ parts) {
+  __shared__ double red[kThreads / 64];
+  const OgSys& S = sy[blockIdx.x];
+  OgState& T = stv[blockIdx.x];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
+  for (int q = threadIdx.x; q < S.nr; q += kThreads) {
+    const float2 x = S.r2[q];
+    v += (double)x.x * x.x + (double)x.y * x.y;
+  }
+  v = bsum(v, red);
+  if (threadIdx.x == 0) {
+    T.J = v;
+    double er = 0.0, ei = 0.0;
+    if (S.est)
+      for (int i = 0; i < S.ns; ++i) {
+        const float2 x = S.t[S.scell[i]];
+        er += S.sw[i] * (double)x.x;
+        ei += S.sw[i] * (double)x.y;
+      }
+    T.eau = make_double2(er, ei);
+  }
+}
+
+// g = -sum over the grid's systems of 2 omega^2 Re(conj(x) r)  (systems idx[0..k))
+__global__ void __launch_bounds__(kThreads) k_og_grad(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
+                                                      const int* __restrict__ idx, int k, int n,
+                                                      float* __restrict__ g) {
   for (int c = blockIdx.x * kThreads + threadIdx.x; c < n; c += gridDim.x * kThreads) {
-    const float2 a = u[c], b = r[c];
-    g[c] = (float)((double)g[c] - 2.0 * w2 * ((double)a.x * b.x + (double)a.y * b.y));
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const int i = idx[j];
+      if (stv[i].status == kBreakdown) continue;
+      const OgSys& S = sy[i];
+      const float2 a = S.x[c], b = S.r[c];
+      acc -= 2.0 * S.omega2 * ((double)a.x * b.x + (double)a.y * b.y);
+    }
+    g[c] = (float)acc;
   }
 }
 
@@ -226,9 +442,8 @@ hipError_t up(void* dst, const std::vector<V>& v, hipStream_t st) {
 int64_t ncell(const wri_grid& g) { return (int64_t)g.nx * g.ny * g.nz; }
 
 struct OgLayout {
-  size_t vec = 0, rvec = 0, dots = 0, tables = 0, total = 0;
-  size_t vb = 0, rb = 0;
-  int dparts = 1;
+  std::vector<size_t> vec, rvec;  // per system: 5 wavefield vectors (x unless u_out), r2 and t2
+  size_t sys = 0, state = 0, parts = 0, idx = 0, total = 0;
 };
 
 int validate_offgrid(const wri_grid* grids, int n_grids, const wri_system* sys, int n_sys, const wri_positions* pos,
@@ -265,20 +480,18 @@ int validate_offgrid(const wri_grid* grids, int n_grids, const wri_system* sys, 
 }
 
 int og_layout(const wri_grid* grids, const wri_system* sys, int n_sys, std::vector<SysTables>* tabs, OgLayout* L) {
-  int64_t nmax = 1, rmax = 1;
-  for (int k = 0; k < n_sys; ++k) {
-    nmax = std::max<int64_t>(nmax, ncell(grids[sys[k].grid]));
-    rmax = std::max<int64_t>(rmax, sys[k].n_rec);
-  }
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = al(o + std::max<size_t>(bytes, 1)); return r; };
-  L->vb = al(sizeof(float2) * (size_t)nmax);
-  L->rb = al(sizeof(float2) * (size_t)rmax);
-  L->vec = take(5 * L->vb);
-  L->rvec = take(2 * L->rb);
-  L->dparts = dot_parts((int)std::max(nmax, rmax));
-  L->dots = take(sizeof(double) * (size_t)(16 + L->dparts));
-  L->tables = o;
+  L->vec.resize(n_sys);
+  L->rvec.resize(n_sys);
+  for (int k = 0; k < n_sys; ++k) {
+    L->vec[k] = take(5 * al(sizeof(float2) * (size_t)ncell(grids[sys[k].grid])));
+    L->rvec[k] = take(2 * al(sizeof(float2) * (size_t)sys[k].n_rec));
+  }
+  L->sys = take(sizeof(OgSys) * (size_t)std::max(n_sys, 1));
+  L->state = take(sizeof(OgState) * (size_t)std::max(n_sys, 1));
+  L->parts = take(sizeof(double) * (size_t)kParts * std::max(n_sys, 1));
+  L->idx = take(sizeof(int) * (size_t)std::max(n_sys, 1));
   for (auto& T : *tabs) {
     T.off = o;
     o = al(o + T.bytes());
@@ -306,186 +519,169 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
   if (ws == nullptr || ws_bytes < L.total)
     return report_error(WRI_ENOWS, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.total);
   char* base = reinterpret_cast<char*>(al(reinterpret_cast<uintptr_t>(ws)));
-  std::vector<DevTables> dt(n_sys);
+  if (J_out) *J_out = 0.0;
+  if (n_sys == 0) {
+    if (grad != nullptr)
+      for (int g = 0; g < n_grids; ++g) OG_HIP(launch_zero_f32(grad[g], (size_t)ncell(grids[g]), st));
+    OG_HIP(hipStreamSynchronize(st));
+    return WRI_OK;
+  }
+  // device tables
+  std::vector<OgSys> hs(n_sys);
+  int64_t nmax = 1;
+  int rmax = 1, umax = 1;
   for (int k = 0; k < n_sys; ++k) {
+    const wri_system& s = sys[k];
+    const wri_grid& g = grids[s.grid];
     const SysTables& T = tabs[k];
-    DevTables& D = dt[k];
-    D = place(base, T);
+    const DevTables D = place(base, T);
     OG_HIP(up(D.scell, T.src.cells, st)); OG_HIP(up(D.sw, T.src.w, st));
     OG_HIP(up(D.rptr, T.rptr, st)); OG_HIP(up(D.rcell, T.rcell, st)); OG_HIP(up(D.rw, T.rw, st));
     OG_HIP(up(D.uptr, T.uptr, st)); OG_HIP(up(D.ucell, T.ucell, st)); OG_HIP(up(D.uq, T.uq, st));
     OG_HIP(up(D.uw, T.uw, st));
+    const int64_t n = ncell(g);
+    const size_t vb = al(sizeof(float2) * (size_t)n);
+    const size_t rb = al(sizeof(float2) * (size_t)s.n_rec);
+    float2* v = reinterpret_cast<float2*>(base + L.vec[k]);
+    OgSys& S = hs[k];
+    S = OgSys{};
+    S.x = (u_out != nullptr && u_out[k] != nullptr) ? reinterpret_cast<float2*>(u_out[k]) : v;
+    S.r = reinterpret_cast<float2*>(base + L.vec[k] + vb);
+    S.p = reinterpret_cast<float2*>(base + L.vec[k] + 2 * vb);
+    S.s = reinterpret_cast<float2*>(base + L.vec[k] + 3 * vb);
+    S.t = reinterpret_cast<float2*>(base + L.vec[k] + 4 * vb);
+    S.r2 = reinterpret_cast<float2*>(base + L.rvec[k]);
+    S.t2 = reinterpret_cast<float2*>(base + L.rvec[k] + rb);
+    S.d = reinterpret_cast<const float2*>(s.d);
+    S.scell = D.scell; S.sw = D.sw;
+    S.rptr = D.rptr; S.rcell = D.rcell; S.rw = D.rw;
+    S.uptr = D.uptr; S.ucell = D.ucell; S.uq = D.uq; S.uw = D.uw;
+    S.n = (int)n;
+    S.ns = (int)T.src.cells.size();
+    S.nr = s.n_rec;
+    S.nu = (int)T.ucell.size();
+    S.est = mode == WRI_ESTIMATE;
+    S.max_iter = max_iter;
+    S.c = (flags & WRI_FLAG_UNSCALED_ALPHA) ? 1.0 : std::sqrt(42.0) / (g.h * g.h);
+    S.lam = s.lambda;
+    S.rtol2 = s.rtol * s.rtol;
+    S.omega2 = s.omega * s.omega;
+    S.alpha = make_double2(s.alpha.re, s.alpha.im);
+    nmax = std::max<int64_t>(nmax, n);
+    rmax = std::max(rmax, S.nr);
+    umax = std::max(umax, S.nu);
   }
+  OgSys* dsys = reinterpret_cast<OgSys*>(base + L.sys);
+  OgState* dst = reinterpret_cast<OgState*>(base + L.state);
+  double* parts = reinterpret_cast<double*>(base + L.parts);
+  int* didx = reinterpret_cast<int*>(base + L.idx);
+  OG_HIP(hipMemcpyAsync(dsys, hs.data(), sizeof(OgSys) * n_sys, hipMemcpyHostToDevice, st));
+  // systems grouped by grid for the gradient pass
+  std::vector<int> order(n_sys);
+  for (int k = 0; k < n_sys; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sys[a].grid < sys[b].grid; });
+  OG_HIP(hipMemcpyAsync(didx, order.data(), sizeof(int) * n_sys, hipMemcpyHostToDevice, st));
   OG_HIP(hipStreamSynchronize(st));  // the host tables are read by the copies above
-  float2* xw = reinterpret_cast<float2*>(base + L.vec);
-  float2* rv = reinterpret_cast<float2*>(base + L.vec + L.vb);
-  float2* pv = reinterpret_cast<float2*>(base + L.vec + 2 * L.vb);
-  float2* sv = reinterpret_cast<float2*>(base + L.vec + 3 * L.vb);
-  float2* tv = reinterpret_cast<float2*>(base + L.vec + 4 * L.vb);
-  float2* r2 = reinterpret_cast<float2*>(base + L.rvec);
-  float2* t2 = reinterpret_cast<float2*>(base + L.rvec + L.rb);
-  double* dres = reinterpret_cast<double*>(base + L.dots);  // [0] |t|^2 [1] |t2|^2 [2] |s|^2 [3] |r2|^2
-  double2* dsrc = reinterpret_cast<double2*>(dres + 8);      // e^H r1, e^H (A u)
-  double* part = dres + 16;                                  // dot-product partials
-  if (grad != nullptr)
-    for (int g = 0; g < n_grids; ++g) OG_HIP(launch_zero_f32(grad[g], (size_t)ncell(grids[g]), st));
-  double Jtot = 0.0;
-  int ret = WRI_OK;
-  for (int k = 0; k < n_sys; ++k) {
+
+  const dim3 vgrid(nblk(nmax), n_sys), rgrid(nblk(rmax), n_sys), ugrid(nblk(umax), n_sys), pgrid(kParts, n_sys);
+  auto stencil = [&](int k, const float2* in, float2* out, int adjoint) -> int {
     const wri_system& s = sys[k];
     const wri_grid& g = grids[s.grid];
-    const DevTables& D = dt[k];
-    const int n = (int)ncell(g);
-    const int nr = s.n_rec;
-    const int ns = (int)tabs[k].src.cells.size();
-    const int nu = (int)tabs[k].ucell.size();
-    const bool est = mode == WRI_ESTIMATE;
-    const double h2inv = 1.0 / (g.h * g.h);
     double sp_scale = 0.0, inv_nb = 0.0;
     if (g.nb > 0) {
       const double d0 = 3.0 * g.v_ref * std::log(1000.0) / (2.0 * g.nb * g.h);
       sp_scale = 2.0 * d0 / (g.v_ref * g.v_ref);
       inv_nb = 1.0 / g.nb;
     }
-    const double c = (flags & WRI_FLAG_UNSCALED_ALPHA) ? 1.0 : std::sqrt(42.0) * h2inv;
-    const double lam = s.lambda;
-    const double rtol2 = s.rtol * s.rtol;
-    float2* x = (u_out != nullptr && u_out[k] != nullptr) ? reinterpret_cast<float2*>(u_out[k]) : xw;
-    const float2 z = make_float2(0.f, 0.f);
-    const int dp = dot_parts(n), dpr = dot_parts(std::max(nr, 1));
-    auto dot = [&](const float2* v, int len, double* out) -> int {
-      const int npp = len == n ? dp : dpr;
-      OG_HIP(launch_dot(v, len, part, npp, st));
-      OG_HIP(launch_sum(part, npp, out, st));
-      return WRI_OK;
-    };
-    // x = 0, r1 = alpha e (KNOWN), r2 = lam d
-    OG_HIP(launch_fill_f2(x, z, n, st));
-    OG_HIP(launch_fill_f2(rv, z, n, st));
-    if (!est && ns > 0) {
-      hipLaunchKernelGGL(k_og_src_set, dim3(1), dim3(64), 0, st, rv, D.scell, D.sw, ns,
-                         make_double2(s.alpha.re, s.alpha.im));
-      OG_HIP(hipGetLastError());
-    }
-    if (nr > 0) {
-      hipLaunchKernelGGL(k_og_r2, dim3(nblk(nr)), dim3(kThreads), 0, st, r2, reinterpret_cast<const float2*>(s.d), nr,
-                         lam);
-      OG_HIP(hipGetLastError());
-    }
-    double hres[4] = {0, 0, 0, 0};
-    double2 hsrc = make_double2(0.0, 0.0);
-    double sa_re = 0.0, sa_im = 0.0;
-    // s = S^H r: wavefield rows A^H r1 + lam P^H r2; source row -c e^H r1
-    auto apply_SH = [&]() -> int {
-      OG_HIP(launch_apply(g.nx, g.ny, g.nz, g.nb, h2inv, sp_scale, inv_nb, s.omega, m[s.grid], rv, sv, 1, -1,
-                          make_double2(0.0, 0.0), st));
-      if (nu > 0) {
-        hipLaunchKernelGGL(k_og_scatter, dim3(nblk(nu)), dim3(kThreads), 0, st, sv, r2, D.uptr, D.ucell, D.uq, D.uw,
-                           nu, lam);
-        OG_HIP(hipGetLastError());
-      }
-      int e = dot(sv, n, dres + 2);
-      if (e != WRI_OK) return e;
-      if (est && ns > 0) {
-        hipLaunchKernelGGL(k_og_src_dot, dim3(1), dim3(64), 0, st, rv, D.scell, D.sw, ns, dsrc);
-        OG_HIP(hipGetLastError());
-      }
-      OG_HIP(hipMemcpyAsync(hres + 2, dres + 2, sizeof(double), hipMemcpyDeviceToHost, st));
-      OG_HIP(hipMemcpyAsync(&hsrc, dsrc, sizeof(double2), hipMemcpyDeviceToHost, st));
-      OG_HIP(hipStreamSynchronize(st));
-      sa_re = (est && ns > 0) ? -c * hsrc.x : 0.0;
-      sa_im = (est && ns > 0) ? -c * hsrc.y : 0.0;
-      return WRI_OK;
-    };
-    rc = apply_SH();
-    if (rc != WRI_OK) return rc;
-    double gamma = hres[2] + sa_re * sa_re + sa_im * sa_im;
-    const double gamma0 = gamma;
-    OG_HIP(launch_copy_f2(pv, sv, n, st));
-    double pa_re = sa_re, pa_im = sa_im, xa_re = 0.0, xa_im = 0.0;
-    int it = 0, status = kActive;
-    while (true) {
-      if (gamma0 == 0.0) { status = kZeroRhs; break; }
-      if (gamma <= rtol2 * gamma0) { status = kConverged; break; }
-      if (it >= max_iter) { status = kMaxIter; break; }
-      // t = S p: A p_u - c p_a e ; t2 = lam P p_u
-      OG_HIP(launch_apply(g.nx, g.ny, g.nz, g.nb, h2inv, sp_scale, inv_nb, s.omega, m[s.grid], pv, tv, 0, -1,
-                          make_double2(0.0, 0.0), st));
-      if (est && ns > 0) {
-        hipLaunchKernelGGL(k_og_src_sub, dim3(1), dim3(64), 0, st, tv, D.scell, D.sw, ns,
-                           make_double2(c * pa_re, c * pa_im));
-        OG_HIP(hipGetLastError());
-      }
-      if (nr > 0) {
-        hipLaunchKernelGGL(k_og_gather, dim3(nblk(nr)), dim3(kThreads), 0, st, t2, pv, D.rptr, D.rcell, D.rw, nr,
-                           lam);
-        OG_HIP(hipGetLastError());
-      }
-      rc = dot(tv, n, dres + 0);
-      if (rc != WRI_OK) return rc;
-      if (nr > 0) {
-        rc = dot(t2, nr, dres + 1);
-        if (rc != WRI_OK) return rc;
-      }
-      OG_HIP(hipMemcpyAsync(hres, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      OG_HIP(hipStreamSynchronize(st));
-      const double delta = hres[0] + (nr > 0 ? hres[1] : 0.0);
-      if (!(delta > 0.0) || !std::isfinite(delta) || !std::isfinite(gamma)) { status = kBreakdown; break; }
-      const double a = gamma / delta;
-      OG_HIP(launch_axpy(x, pv, a, n, st));
-      OG_HIP(launch_axpy(rv, tv, -a, n, st));
-      OG_HIP(launch_axpy(r2, t2, -a, nr, st));
-      xa_re += a * pa_re;
-      xa_im += a * pa_im;
-      rc = apply_SH();
-      if (rc != WRI_OK) return rc;
-      const double gnew = hres[2] + sa_re * sa_re + sa_im * sa_im;
-      const double beta = gnew / gamma;
-      gamma = gnew;
-      OG_HIP(launch_xpby(pv, sv, beta, n, st));
-      pa_re = sa_re + beta * pa_re;
-      pa_im = sa_im + beta * pa_im;
-      ++it;
-    }
-    // objective from the recurred residuals, gradient, source weights
-    rc = dot(rv, n, dres + 0);
-    if (rc != WRI_OK) return rc;
-    if (nr > 0) {
-      rc = dot(r2, nr, dres + 3);
-      if (rc != WRI_OK) return rc;
-    }
-    if (grad != nullptr && status != kBreakdown) {
-      hipLaunchKernelGGL(k_og_grad, dim3(nblk(n)), dim3(kThreads), 0, st, grad[s.grid], x, rv, n,
-                         s.omega * s.omega);
-      OG_HIP(hipGetLastError());
-    }
-    double2 eau = make_double2(0.0, 0.0);
-    if (est && ns > 0) {  // alpha_ls = e^H (A u) / e^H e
-      OG_HIP(launch_apply(g.nx, g.ny, g.nz, g.nb, h2inv, sp_scale, inv_nb, s.omega, m[s.grid], x, tv, 0, -1,
-                          make_double2(0.0, 0.0), st));
-      hipLaunchKernelGGL(k_og_src_dot, dim3(1), dim3(64), 0, st, tv, D.scell, D.sw, ns, dsrc + 1);
-      OG_HIP(hipGetLastError());
-      OG_HIP(hipMemcpyAsync(&eau, dsrc + 1, sizeof(double2), hipMemcpyDeviceToHost, st));
-    }
-    OG_HIP(hipMemcpyAsync(hres, dres, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    OG_HIP(launch_apply(g.nx, g.ny, g.nz, g.nb, 1.0 / (g.h * g.h), sp_scale, inv_nb, s.omega, m[s.grid], in, out,
+                        adjoint, -1, make_double2(0.0, 0.0), st));
+    return WRI_OK;
+  };
+  // set-up: x = 0, r = b, s = S^H b
+  hipLaunchKernelGGL(k_og_zero, vgrid, dim3(kThreads), 0, st, dsys);
+  OG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_og_init, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst);
+  OG_HIP(hipGetLastError());
+  for (int k = 0; k < n_sys; ++k)
+    if ((rc = stencil(k, hs[k].r, hs[k].s, 1)) != WRI_OK) return rc;
+  hipLaunchKernelGGL(k_og_scatter, ugrid, dim3(kThreads), 0, st, dsys, dst, 1);
+  hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 1, 1, parts);
+  hipLaunchKernelGGL(k_og_start, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
+  hipLaunchKernelGGL(k_og_copy_ps, vgrid, dim3(kThreads), 0, st, dsys);
+  OG_HIP(hipGetLastError());
+  std::vector<OgState> hst(n_sys);
+  auto read = [&]() -> int {
+    OG_HIP(hipMemcpyAsync(hst.data(), dst, sizeof(OgState) * n_sys, hipMemcpyDeviceToHost, st));
     OG_HIP(hipStreamSynchronize(st));
+    return WRI_OK;
+  };
+  if ((rc = read()) != WRI_OK) return rc;
+  std::vector<int> active;
+  for (int64_t done = 0;; done += kCheck) {
+    active.clear();
+    for (int k = 0; k < n_sys; ++k)
+      if (hst[k].status == kActive) active.push_back(k);
+    if (active.empty()) break;
+    if (done > (int64_t)max_iter + kCheck) return report_error(WRI_EHIP, "internal: systems active past max_iter");
+    for (int it = 0; it < kCheck; ++it) {
+      for (int k : active)
+        if ((rc = stencil(k, hs[k].p, hs[k].t, 0)) != WRI_OK) return rc;
+      hipLaunchKernelGGL(k_og_src_sub, dim3(n_sys), dim3(64), 0, st, dsys, dst);
+      hipLaunchKernelGGL(k_og_gather, rgrid, dim3(kThreads), 0, st, dsys, dst);
+      hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 0, 0, parts);
+      hipLaunchKernelGGL(k_og_alpha, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
+      hipLaunchKernelGGL(k_og_update, vgrid, dim3(kThreads), 0, st, dsys, dst);
+      OG_HIP(hipGetLastError());
+      for (int k : active)
+        if ((rc = stencil(k, hs[k].r, hs[k].s, 1)) != WRI_OK) return rc;
+      hipLaunchKernelGGL(k_og_scatter, ugrid, dim3(kThreads), 0, st, dsys, dst, 0);
+      hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 1, 0, parts);
+      hipLaunchKernelGGL(k_og_beta, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
+      hipLaunchKernelGGL(k_og_xpby, vgrid, dim3(kThreads), 0, st, dsys, dst);
+      OG_HIP(hipGetLastError());
+    }
+    if ((rc = read()) != WRI_OK) return rc;
+  }
+  // objective, source weights, gradient
+  hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 2, 1, parts);
+  OG_HIP(hipGetLastError());
+  if (mode == WRI_ESTIMATE)
+    for (int k = 0; k < n_sys; ++k)
+      if ((rc = stencil(k, hs[k].x, hs[k].t, 0)) != WRI_OK) return rc;
+  hipLaunchKernelGGL(k_og_final, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
+  OG_HIP(hipGetLastError());
+  if (grad != nullptr)
+    for (int g = 0, p0 = 0; g < n_grids; ++g) {
+      int cnt = 0;
+      while (p0 + cnt < n_sys && sys[order[p0 + cnt]].grid == g) ++cnt;
+      const int64_t n = ncell(grids[g]);
+      hipLaunchKernelGGL(k_og_grad, dim3(nblk(n)), dim3(kThreads), 0, st, dsys, dst, didx + p0, cnt, (int)n,
+                         grad[g]);
+      OG_HIP(hipGetLastError());
+      p0 += cnt;
+    }
+  if ((rc = read()) != WRI_OK) return rc;
+  double Jtot = 0.0;
+  int ret = WRI_OK;
+  for (int k = 0; k < n_sys; ++k) {
+    const OgState& T = hst[k];
     double ee = 0.0;
     for (double w : tabs[k].src.w) ee += w * w;
     wri_result& r = res[k];
-    r.iters = it;
-    r.status = status;
-    r.relres = gamma0 > 0.0 ? std::sqrt(std::max(gamma, 0.0) / gamma0) : 0.0;
-    r.J = hres[0] + (nr > 0 ? hres[3] : 0.0);
-    if (est) {
-      r.alpha = wri_c64{c * xa_re, c * xa_im};
-      r.alpha_ls = ee > 0.0 ? wri_c64{eau.x / ee, eau.y / ee} : wri_c64{0.0, 0.0};
+    r.iters = T.iters;
+    r.status = T.status;
+    r.relres = T.gamma0 > 0.0 ? std::sqrt(std::max(T.gamma, 0.0) / T.gamma0) : 0.0;
+    r.J = T.J;
+    if (mode == WRI_ESTIMATE) {
+      r.alpha = wri_c64{hs[k].c * T.xa.x, hs[k].c * T.xa.y};
+      r.alpha_ls = ee > 0.0 ? wri_c64{T.eau.x / ee, T.eau.y / ee} : wri_c64{0.0, 0.0};
     } else {
-      r.alpha = s.alpha;
-      r.alpha_ls = s.alpha;
+      r.alpha = sys[k].alpha;
+      r.alpha_ls = sys[k].alpha;
     }
-    Jtot += r.J;
-    if (status == kBreakdown) ret = WRI_EBREAKDOWN;
-    else if (status == kMaxIter && ret == WRI_OK) ret = WRI_NOT_CONVERGED;
+    Jtot += T.J;
+    if (T.status == kBreakdown) ret = WRI_EBREAKDOWN;
+    else if (T.status == kMaxIter && ret == WRI_OK) ret = WRI_NOT_CONVERGED;
   }
   if (J_out) *J_out = Jtot;
   if (ret == WRI_EBREAKDOWN) report_error(WRI_EBREAKDOWN, "at least one system broke down");
