@@ -516,6 +516,56 @@ def wri_objective(batch: Batch, *ms, mode=None, max_iter=20000, flags=0):
     return WRIObjective.apply(batch, batch.mode if mode is None else mode, max_iter, flags, *ms)
 
 
+class FWIObjective(torch.autograd.Function):
+    """Reduced FWI objective f(m) (eq. FWI2) of the batch, differentiable in
+    m: forward runs wri_fwi_objective_grad (forward and adjoint solves);
+    backward returns grad_output * df/dm."""
+
+    @staticmethod
+    def forward(ctx, batch: Batch, mode, max_iter, flags, *ms):
+        batch.set_m(ms)
+        f, grads, res = fwi_objective_grad(batch, mode=mode, max_iter=max_iter, flags=flags)
+        ctx.save_for_backward(*grads)
+        ctx.shapes = [m.shape for m in ms]
+        batch.last_results = res
+        return torch.tensor(f, dtype=torch.float64, device=ms[0].device)
+
+    @staticmethod
+    def backward(ctx, gf):
+        grads = ctx.saved_tensors
+        out = [(gf.to(torch.float32) * g).reshape(s) for g, s in zip(grads, ctx.shapes)]
+        return (None, None, None, None, *out)
+
+
+def fwi_objective(batch: Batch, *ms, mode=None, max_iter=20000, flags=0):
+    """Functional form of FWIObjective."""
+    return FWIObjective.apply(batch, batch.mode if mode is None else mode, max_iter, flags, *ms)
+
+
+class ModelGridObjective(torch.autograd.Function):
+    """J(m_model) with every simulation grid's model resampled from one model
+    grid, differentiable in m_model (wri_objective_grad_model)."""
+
+    @staticmethod
+    def forward(ctx, batch: Batch, model_grid, mode, max_iter, flags, m_model):
+        J, g, res = objective_grad_model(batch, model_grid, m_model, mode=mode, max_iter=max_iter, flags=flags)
+        ctx.save_for_backward(g)
+        ctx.shape = m_model.shape
+        batch.last_results = res
+        return torch.tensor(J, dtype=torch.float64, device=m_model.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (g,) = ctx.saved_tensors
+        return (None, None, None, None, None, (gJ.to(torch.float32) * g).reshape(ctx.shape))
+
+
+def model_grid_objective(batch: Batch, model_grid, m_model: torch.Tensor, mode=None, max_iter=20000, flags=0):
+    """Functional form of ModelGridObjective."""
+    return ModelGridObjective.apply(batch, model_grid, batch.mode if mode is None else mode, max_iter, flags,
+                                    m_model)
+
+
 # --------------------------------------------------------------------------
 # outer loop: TV, l-BFGS direction, Algorithm 2 (adaptive tolerance)
 # --------------------------------------------------------------------------

@@ -137,3 +137,17 @@ def test_fwi_zero_at_the_data_generating_model():
     b.set_m([torch.as_tensor(p.m[0] * 1.03, dtype=torch.float32)])
     _, gp, _ = wri.fwi_objective_grad(b)
     assert grads[0].abs().max().item() <= 1e-2 * gp[0].abs().max().item()
+
+
+def test_fwi_autograd_function():
+    """FWIObjective: backward returns grad_output times the library gradient."""
+    _say("fwi autograd")
+    p = _fwi_problem(shape=(33, 20, 14), seed=57, freqs=(12.0,))
+    b = wri.Batch(p, device=DEV)
+    m = torch.tensor(p.m[0].reshape(-1), dtype=torch.float32, device=DEV, requires_grad=True)
+    f = wri.fwi_objective(b, m)
+    (3.0 * f).backward()
+    b2 = wri.Batch(p, device=DEV)
+    f2, g2, _ = wri.fwi_objective_grad(b2)
+    assert abs(f.item() - f2) <= 1e-12 * abs(f2)
+    assert torch.allclose(m.grad, 3.0 * g2[0], rtol=1e-6, atol=0)

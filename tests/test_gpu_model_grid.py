@@ -102,3 +102,15 @@ def test_objective_grad_on_the_model_grid_matches_oracle(mode):
     b.set_m([wri.model_to_grid(mgrid, torch.tensor(m_model.reshape(-1), device=DEV), gr) for gr in p.grids])
     J2, _, _ = wri.objective_grad(b)
     assert abs(J2 - J) <= 1e-12 * abs(J)
+
+
+def test_model_grid_autograd_function():
+    _say("model grid autograd")
+    mgrid, p, m_model = _model_problem()
+    b = wri.Batch(p, device=DEV)
+    m = torch.tensor(m_model.reshape(-1), device=DEV, requires_grad=True)
+    J = wri.model_grid_objective(b, mgrid, m)
+    (0.5 * J).backward()
+    J2, g2, _ = wri.objective_grad_model(b, mgrid, torch.tensor(m_model.reshape(-1), device=DEV))
+    assert J.item() == J2
+    assert torch.allclose(m.grad, 0.5 * g2, rtol=1e-6, atol=0)
