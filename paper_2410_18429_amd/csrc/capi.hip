@@ -68,6 +68,7 @@ const TileCfg kCands[] = {
     {8, 1, 32, 1, 0}, {8, 1, 32, 1, 1}, {8, 1, 16, 1, 1}, {8, 2, 32, 1, 0}, {8, 2, 32, 1, 1},
     {4, 1, 32, 1, 1}, {4, 1, 64, 1, 1}, {4, 4, 32, 1, 1}, {4, 2, 32, 0, 1}, {8, 1, 16, 0, 1},
     {8, 2, 16, 0, 1}, {4, 2, 16, 0, 0}, {8, 1, 16, 0, 0}, {2, 8, 32, 0, 0}, {4, 4, 16, 0, 1},
+    {8, 1, 32, 1, 2}, {8, 1, 32, 1, 4}, {8, 1, 32, 1, 8}, {4, 2, 32, 1, 2},
 };
 constexpr int kNumCands = sizeof(kCands) / sizeof(kCands[0]);
 

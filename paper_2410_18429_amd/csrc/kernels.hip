@@ -65,6 +65,33 @@ __device__ __forceinline__ int2 ld2i(const GLOBAL int2* p, int i) {
   return __builtin_bit_cast(int2, *((const GLOBAL unsigned long long*)p + i));
 }
 
+// Block order inside a group: system-major (tile_major 0: all tiles of one
+// system, then the next), tile-major over all systems (1), or tile-major
+// within bundles of tile_major >= 2 systems (the same tile of the bundle's
+// systems on consecutive blocks, so the bundle shares m and its halo rows in
+// L2; the last bundle may be smaller).
+__device__ __forceinline__ void block_map(const GroupDesc& d, int local, int* rl, int* tile) {
+  const int n = d.nrhs, nt = d.ntiles, ord = d.tile_major;
+  if (ord == 0) {
+    *rl = local / nt;
+    *tile = local - *rl * nt;
+    return;
+  }
+  const int bsz = (ord == 1 || ord > n) ? n : ord;
+  const int full = n / bsz, span = bsz * nt;
+  const int b = local / span;
+  if (b < full) {
+    const int w = local - b * span;
+    *tile = w / bsz;
+    *rl = b * bsz + (w - *tile * bsz);
+  } else {
+    const int bt = n - full * bsz;
+    const int w = local - full * span;
+    *tile = w / bt;
+    *rl = full * bsz + (w - *tile * bt);
+  }
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb, int q) {
   // Blocks go round-robin to the XCDs (b % 8).  The logical sequence of
   // (group, system, tile) is cut into chunks of q consecutive tiles, dealt to the
@@ -380,9 +407,8 @@ k_fwd(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
   const int local = logical - gd[g].block0;
-  const int nrhs_g = gd[g].nrhs;
-  const int rl = gd[g].tile_major ? (local % nrhs_g) : (local / ntiles);
-  const int tile = gd[g].tile_major ? (local / nrhs_g) : (local - rl * ntiles);
+  int rl, tile;
+  block_map(gd[g], local, &rl, &tile);
   const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
@@ -587,9 +613,8 @@ k_adj(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double*
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
   const int local = logical - gd[g].block0;
-  const int nrhs_g = gd[g].nrhs;
-  const int rl = gd[g].tile_major ? (local % nrhs_g) : (local / ntiles);
-  const int tile = gd[g].tile_major ? (local / nrhs_g) : (local - rl * ntiles);
+  int rl, tile;
+  block_map(gd[g], local, &rl, &tile);
   const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
@@ -833,9 +858,8 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
   const int local = logical - gd[g].block0;
-  const int nrhs_g = gd[g].nrhs;
-  const int rl = gd[g].tile_major ? (local % nrhs_g) : (local / ntiles);
-  const int tile = gd[g].tile_major ? (local / nrhs_g) : (local - rl * ntiles);
+  int rl, tile;
+  block_map(gd[g], local, &rl, &tile);
   const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;
@@ -1104,9 +1128,8 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
   const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
   const int local = logical - gd[g].block0;
-  const int nrhs_g = gd[g].nrhs;
-  const int rl = gd[g].tile_major ? (local % nrhs_g) : (local / ntiles);
-  const int tile = gd[g].tile_major ? (local / nrhs_g) : (local - rl * ntiles);
+  int rl, tile;
+  block_map(gd[g], local, &rl, &tile);
   const int rhs = gd[g].rhs0 + rl;
   const SysDev& S = sysv[rhs];
   SysState* T = stv + rhs;

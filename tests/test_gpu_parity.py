@@ -411,7 +411,7 @@ def test_full_size_differentiation_workload():
 # --------------------------------------------------------------------------
 
 TILES = ["4,4,32,0,0", "4,4,32,1,1", "4,2,32,0,1", "4,2,32,1,1", "4,2,32,1,0", "4,2,16,0,0", "8,1,32,1,1",
-         "8,2,32,1,0", "2,8,32,0,0", "4,1,64,1,1"]
+         "8,2,32,1,0", "2,8,32,0,0", "4,1,64,1,1", "8,1,32,1,2", "8,1,32,1,4", "4,2,32,1,2"]
 
 
 def test_large_workload_frequency_batch():
@@ -484,6 +484,26 @@ def test_tile_invariance(monkeypatch):
     for a, b in (("4,2,32,0,1", "4,2,32,1,1"), ("4,2,32,1,0", "4,2,32,1,1")):
         for i in range(len(p.systems)):
             assert torch.equal(outs[a][0][i], outs[b][0][i]), (a, b, i)
+
+
+def test_block_orders_give_identical_bits(monkeypatch):
+    """System-major, tile-major and bundled block orders (bundles of 2, 4 and
+    8 over 5 systems: full and ragged bundles) only change which block does
+    which (system, tile): every tile's arithmetic and the fixed-order sums of
+    the per-tile partials are the same, so the results are bit-identical."""
+    _say("block orders")
+    p = wri_synth.custom_problem((70, 20, 12), nb=2, n_src=5, n_rec=8, seed=23, freqs=(9.0,), rtol=0.0)
+    outs = {}
+    for t in ("8,1,32,1,0", "8,1,32,1,1", "8,1,32,1,2", "8,1,32,1,4", "8,1,32,1,8"):
+        monkeypatch.setenv("WRI_TILE", t)
+        u, res = wri.solve(wri.Batch(p, device=DEV), max_iter=14)
+        outs[t] = (u, res)
+    monkeypatch.delenv("WRI_TILE")
+    ref = outs["8,1,32,1,0"]
+    for t, (u, res) in outs.items():
+        for i in range(len(p.systems)):
+            assert torch.equal(u[i], ref[0][i]), (t, i)
+            assert res[i]["alpha"] == ref[1][i]["alpha"], (t, i)
 
 
 def test_uneven_workload_one_launch():
