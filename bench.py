@@ -45,14 +45,17 @@ BYTES_NOTE = {"fwd": "36, +24 on even iterations (x update of two steps)", "adj"
 # kernels.hip + capi.hip + wri_impl.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "83d7564c413c753b",
+    "sources_sha256": "b4cb90702adbf97b",
     "tiles": {
-        "8,1,32,1,0": {"fwd_x": {"fetch_kib": 2018831.1, "write_kib": 2359557.8},
-                       "fwd": {"fetch_kib": 1199676.2, "write_kib": 1573088.8},
-                       "adj": {"fetch_kib": 1184600.7, "write_kib": 1573103.8}},
-        "4,2,32,1,0": {"fwd_x": {"fetch_kib": 2059242.8, "write_kib": 2359676.2},
-                       "fwd": {"fetch_kib": 1224766.8, "write_kib": 1573146.2},
-                       "adj": {"fetch_kib": 1246132.0, "write_kib": 1573207.5}},
+        "8,1,32,1,4": {"fwd_x": {"fetch_kib": 1844788.1, "write_kib": 2359536.5},
+                       "fwd": {"fetch_kib": 1029700.1, "write_kib": 1573055.5},
+                       "adj": {"fetch_kib": 1011438.7, "write_kib": 1573100.0}},
+        "8,1,32,1,0": {"fwd_x": {"fetch_kib": 2018144.9, "write_kib": 2359560.8},
+                       "fwd": {"fetch_kib": 1201010.1, "write_kib": 1573086.4},
+                       "adj": {"fetch_kib": 1185935.4, "write_kib": 1573104.1}},
+        "4,2,32,1,0": {"fwd_x": {"fetch_kib": 2060307.0, "write_kib": 2359674.6},
+                       "fwd": {"fetch_kib": 1224300.9, "write_kib": 1573148.4},
+                       "adj": {"fetch_kib": 1245184.7, "write_kib": 1573206.4}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
