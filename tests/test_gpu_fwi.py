@@ -151,3 +151,20 @@ def test_fwi_autograd_function():
     f2, g2, _ = wri.fwi_objective_grad(b2)
     assert abs(f.item() - f2) <= 1e-12 * abs(f2)
     assert torch.allclose(m.grad, 3.0 * g2[0], rtol=1e-6, atol=0)
+
+
+def test_entry_points_with_no_systems():
+    """No systems: the FWI baseline, the model-grid objective and the off-grid
+    objective return 0 and zero gradients (the outputs are overwritten)."""
+    _say("no systems")
+    p = _fwi_problem(shape=(20, 12, 10), seed=58, freqs=(12.0,))
+    p0 = dataclasses.replace(p, systems=[])
+    b = wri.Batch(p0, device=DEV)
+    g = torch.full((p.grids[0].n,), 7.0, dtype=torch.float32, device=DEV)
+    f, grads, res = wri.fwi_objective_grad(b, grad_out=[g])
+    assert f == 0.0 and res == [] and torch.count_nonzero(grads[0]).item() == 0
+    J, go, res = wri.objective_grad_offgrid(b, [], [])
+    assert J == 0.0 and torch.count_nonzero(go[0]).item() == 0
+    mgrid = wri_synth.Grid(20, 12, 10, 10.0, 0, 1500.0)
+    J, gm, res = wri.objective_grad_model(b, mgrid, torch.full((mgrid.n,), 3e-7, device=DEV))
+    assert J == 0.0 and torch.count_nonzero(gm).item() == 0
