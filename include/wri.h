@@ -322,7 +322,8 @@ typedef struct {
 size_t wri_fwi_workspace_bytes(const wri_grid* grids, int32_t n_grids, const wri_system* sys, int32_t n_sys,
                                int32_t mode, int32_t flags);
 /*   m[g]     DEVICE float32 n(g) per grid (host array of n_grids pointers)
- *   flags    WRI_FLAG_PLAIN / NO_GRAPH / NO_AUTOTUNE / TIMING (not WARM_START)
+ *   flags    WRI_FLAG_PLAIN / NO_GRAPH / NO_AUTOTUNE / TIMING (not WARM_START); with
+ *            TIMING, wri_kernel_times() then reports the adjoint (last) solve
  *   f_out    HOST double: sum of the systems' f (required)
  *   grad     host array of n_grids DEVICE float32 pointers receiving df/dm
  *            (overwritten; zeros on grids without systems), or NULL
