@@ -321,6 +321,43 @@ def offgrid_bench(name, steps, dev):
                                   f"positions moved up to half a cell", "steps": steps, **out}))
 
 
+def large_bench(freq, rtol, dev):
+    """The large workload (256 x 256 x 192, 12.6 M cells per system) one
+    frequency band at a time (64 systems, 45 GB of solver vectors): time of an
+    objective-and-gradient evaluation and the fused kernels' rates (HIP events
+    around every launch in a second, timed evaluation)."""
+    import torch
+    import wri_synth
+    from paper_2410_18429_amd import wri
+    p = wri_synth.make_config("large", seed=0)
+    band = [k for k, s in enumerate(p.systems) if s.freq == freq]
+    q = p.subset(band).with_rtol(rtol)
+    g = q.grids[0]
+    b = wri.Batch(q, device=dev)
+    wri.objective_grad(b)   # warm-up: autotuner and graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, _, res = wri.objective_grad(b)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    it = [r["iters"] for r in res]
+    wri.objective_grad(b, flags=wri.FLAG_TIMING)
+    torch.cuda.synchronize()
+    kt = wri.kernel_times()
+    out = {"seconds_per_eval": round(sec, 3), "solves_per_s": round(len(band) / sec, 3),
+           "iters_mean": float(np.mean(it)), "iters_max": int(max(it)),
+           "status": sorted(set(r["status"] for r in res)),
+           "fwd_gbs": round(kt["fwd_bytes"] / (kt["fwd_ms"] * 1e-3) / 1e9, 1),
+           "adj_gbs": round(kt["adj_bytes"] / (kt["adj_ms"] * 1e-3) / 1e9, 1),
+           "fwd_gbs_full_batch": round(kt["fwd_bytes_full"] / (kt["fwd_ms_full"] * 1e-3) / 1e9, 1),
+           "adj_gbs_full_batch": round(kt["adj_bytes_full"] / (kt["adj_ms_full"] * 1e-3) / 1e9, 1),
+           "tile": f"{kt['tile_w']},{kt['tile_ry']},{kt['tile_tz']},{kt['tile_pf']},{kt['tile_order']}"}
+    print(f"[large] {out}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "large workload, one frequency band per call",
+                      "workload": f"large: {g.nx}x{g.ny}x{g.nz}, {len(band)} systems at {freq:g} Hz, ESTIMATE, "
+                                  f"rtol {rtol:g}", **out}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +379,10 @@ def main():
                          "grid tied to its three simulation grids")
     ap.add_argument("--offgrid", action="store_true",
                     help="off-grid source/receiver measurement instead of the headline (--config, default medium)")
+    ap.add_argument("--large-band", type=float, default=0.0,
+                    help="large-workload measurement instead of the headline: the 64-system band at this "
+                         "frequency (4, 6, ..., 14 Hz) at --large-rtol")
+    ap.add_argument("--large-rtol", type=float, default=1e-3)
     ap.add_argument("--fwi", action="store_true",
                     help="reduced-FWI baseline measurement instead of the headline: objective-and-gradient "
                          "evaluations of FWI and WRI on --config")
@@ -375,6 +416,9 @@ def main():
         return
     if args.model_grid:
         model_grid_bench(args.steps, dev)
+        return
+    if args.large_band > 0:
+        large_bench(args.large_band, args.large_rtol, dev)
         return
     if args.offgrid:
         offgrid_bench("medium" if args.config == "differentiation" else args.config, args.steps, dev)
