@@ -358,6 +358,58 @@ def large_bench(freq, rtol, dev):
                                   f"rtol {rtol:g}", **out}))
 
 
+def large_gd_bench(n_iter, dev, start=0, m_in="", m_out=""):
+    """The large workload's protocol: 10 outer gradient-descent iterations over
+    all six frequency bands (64 systems each, one call per band), the solver
+    tolerance tightened as rtol_k = 1e-2 (1e-3)^(k/9), each iteration the full
+    objective, gradient and source-weight estimate of all 384 systems, then
+    m <- m - 0.01 max|m0| g / max|g|.  Reports latency per iteration and the
+    fused kernels' rates (HIP events around every launch)."""
+    import torch
+    import wri_synth
+    from paper_2410_18429_amd import wri
+    p = wri_synth.make_config("large", seed=0)
+    freqs = sorted(set(s.freq for s in p.systems))
+    bands = [[k for k, s in enumerate(p.systems) if s.freq == f] for f in freqs]
+    m0 = np.asarray(p.m[0], dtype=np.float32).reshape(-1)
+    step = 0.01 * float(np.abs(m0).max())
+    # a run may continue an earlier one (iterations start.. with its model)
+    m = torch.tensor(np.load(m_in) if m_in else m0, device=dev)
+    rows = []
+    for it in range(start, start + n_iter):
+        rtol = 1e-2 * (1e-3) ** (it / 9.0)
+        t0 = time.perf_counter()
+        J = 0.0
+        g = torch.zeros_like(m)
+        fb = fms = ab = ams = 0.0
+        iters = []
+        for band in bands:
+            b = wri.Batch(p.subset(band).with_rtol(rtol), device=dev, m=[m])
+            Jb, gb, res = wri.objective_grad(b, flags=wri.FLAG_TIMING)
+            kt = wri.kernel_times()
+            fb += kt["fwd_bytes"]; fms += kt["fwd_ms"]; ab += kt["adj_bytes"]; ams += kt["adj_ms"]
+            J += Jb
+            g += gb[0]
+            iters += [r["iters"] for r in res]
+            del b, gb
+            print(f"[large-gd] iteration {it} band {p.systems[band[0]].freq:g} Hz: "
+                  f"{time.perf_counter() - t0:.1f} s so far, max iterations {max(r['iters'] for r in res)}",
+                  file=sys.stderr, flush=True)
+        m -= step * g / g.abs().max()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        rows.append({"iteration": it, "rtol": float(f"{rtol:.3g}"), "seconds": round(sec, 2), "J": J,
+                     "cgls_iterations_mean": round(float(np.mean(iters)), 1), "cgls_iterations_max": int(max(iters)),
+                     "fwd_gbs": round(fb / (fms * 1e-3) / 1e9, 1), "adj_gbs": round(ab / (ams * 1e-3) / 1e9, 1)})
+        print(f"[large-gd] {rows[-1]}", file=sys.stderr, flush=True)
+        if m_out:
+            np.save(m_out, m.cpu().numpy())
+    print(json.dumps({"metric": "large workload: latency per outer gradient-descent iteration",
+                      "workload": "large: 256x256x192, 384 systems (64 sources x 6 frequencies, one call per band), "
+                                  "ESTIMATE", "iterations": rows,
+                      "total_seconds": round(sum(r["seconds"] for r in rows), 2)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,6 +435,12 @@ def main():
                     help="large-workload measurement instead of the headline: the 64-system band at this "
                          "frequency (4, 6, ..., 14 Hz) at --large-rtol")
     ap.add_argument("--large-rtol", type=float, default=1e-3)
+    ap.add_argument("--large-gd", type=int, default=0,
+                    help="the large workload's gradient-descent protocol for this many outer iterations (10)")
+    ap.add_argument("--large-gd-start", type=int, default=0,
+                    help="first outer iteration (a continued run loads its model with --large-gd-m-in)")
+    ap.add_argument("--large-gd-m-in", default="", help="model (.npy, float32) to continue from")
+    ap.add_argument("--large-gd-m-out", default="", help="write the model after every outer iteration (.npy)")
     ap.add_argument("--fwi", action="store_true",
                     help="reduced-FWI baseline measurement instead of the headline: objective-and-gradient "
                          "evaluations of FWI and WRI on --config")
@@ -416,6 +474,9 @@ def main():
         return
     if args.model_grid:
         model_grid_bench(args.steps, dev)
+        return
+    if args.large_gd > 0:
+        large_gd_bench(args.large_gd, dev, args.large_gd_start, args.large_gd_m_in, args.large_gd_m_out)
         return
     if args.large_band > 0:
         large_bench(args.large_band, args.large_rtol, dev)
