@@ -358,7 +358,7 @@ def large_bench(freq, rtol, dev):
                                   f"rtol {rtol:g}", **out}))
 
 
-def large_gd_bench(n_iter, dev, start=0, m_in="", m_out=""):
+def large_gd_bench(n_iter, dev, start=0, m_in="", m_out="", warm=False):
     """The large workload's protocol: 10 outer gradient-descent iterations over
     all six frequency bands (64 systems each, one call per band), the solver
     tolerance tightened as rtol_k = 1e-2 (1e-3)^(k/9), each iteration the full
@@ -376,6 +376,11 @@ def large_gd_bench(n_iter, dev, start=0, m_in="", m_out=""):
     # a run may continue an earlier one (iterations start.. with its model)
     m = torch.tensor(np.load(m_in) if m_in else m0, device=dev)
     rows = []
+    # warm: every system keeps its wavefield and source weight between outer
+    # iterations and starts its next solve there (zeros at the first)
+    keep_u = [[torch.zeros(p.grids[0].n, dtype=torch.complex64, device=dev) for _ in band] for band in bands] \
+        if warm else None
+    keep_a = [[0j for _ in band] for band in bands] if warm else None
     for it in range(start, start + n_iter):
         rtol = 1e-2 * (1e-3) ** (it / 9.0)
         t0 = time.perf_counter()
@@ -383,9 +388,14 @@ def large_gd_bench(n_iter, dev, start=0, m_in="", m_out=""):
         g = torch.zeros_like(m)
         fb = fms = ab = ams = 0.0
         iters = []
-        for band in bands:
+        for bi, band in enumerate(bands):
             b = wri.Batch(p.subset(band).with_rtol(rtol), device=dev, m=[m])
-            Jb, gb, res = wri.objective_grad(b, flags=wri.FLAG_TIMING)
+            if warm:
+                b.set_alpha(keep_a[bi])
+                Jb, gb, res = wri.objective_grad(b, flags=wri.FLAG_TIMING | wri.FLAG_WARM_START, u_out=keep_u[bi])
+                keep_a[bi] = [r["alpha"] for r in res]
+            else:
+                Jb, gb, res = wri.objective_grad(b, flags=wri.FLAG_TIMING)
             kt = wri.kernel_times()
             fb += kt["fwd_bytes"]; fms += kt["fwd_ms"]; ab += kt["adj_bytes"]; ams += kt["adj_ms"]
             J += Jb
@@ -406,7 +416,7 @@ def large_gd_bench(n_iter, dev, start=0, m_in="", m_out=""):
             np.save(m_out, m.cpu().numpy())
     print(json.dumps({"metric": "large workload: latency per outer gradient-descent iteration",
                       "workload": "large: 256x256x192, 384 systems (64 sources x 6 frequencies, one call per band), "
-                                  "ESTIMATE", "iterations": rows,
+                                  "ESTIMATE" + (", warm-started solves" if warm else ""), "iterations": rows,
                       "total_seconds": round(sum(r["seconds"] for r in rows), 2)}))
 
 
@@ -441,6 +451,8 @@ def main():
                     help="first outer iteration (a continued run loads its model with --large-gd-m-in)")
     ap.add_argument("--large-gd-m-in", default="", help="model (.npy, float32) to continue from")
     ap.add_argument("--large-gd-m-out", default="", help="write the model after every outer iteration (.npy)")
+    ap.add_argument("--large-gd-warm", action="store_true",
+                    help="start every solve from the system's wavefield and weight of the previous outer iteration")
     ap.add_argument("--fwi", action="store_true",
                     help="reduced-FWI baseline measurement instead of the headline: objective-and-gradient "
                          "evaluations of FWI and WRI on --config")
@@ -476,7 +488,8 @@ def main():
         model_grid_bench(args.steps, dev)
         return
     if args.large_gd > 0:
-        large_gd_bench(args.large_gd, dev, args.large_gd_start, args.large_gd_m_in, args.large_gd_m_out)
+        large_gd_bench(args.large_gd, dev, args.large_gd_start, args.large_gd_m_in, args.large_gd_m_out,
+                       args.large_gd_warm)
         return
     if args.large_band > 0:
         large_bench(args.large_band, args.large_rtol, dev)
