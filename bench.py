@@ -42,7 +42,7 @@ BYTES_NOTE = {"fwd": "36, +24 on even iterations (x update of two steps)", "adj"
 # probe with the tile forced), each scaled by what the counter reads for a 1 GiB device copy
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  "fwd_x" is the forward launch that also updates x
 # (even iterations).  Valid only for the solver sources it was measured on (sha256 prefix of
-# kernels.hip + capi.hip + wri_impl.hpp) and for the tile shape in the key;
+# kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
     "sources_sha256": "b4cb90702adbf97b",
@@ -64,7 +64,7 @@ TRAFFIC = {
 def _sources_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "capi.hip", "wri_impl.hpp"):
+    for f in ("kernels.hip", "capi.hip", "wri_impl.hpp", "stencil.hpp"):
         with open(os.path.join(ROOT, "paper_2410_18429_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -388,10 +388,10 @@ int wri_objective_grad_model(const wri_grid* model_grid, const float* m_model, c
  * -c e and the least-squares weight of the result is
  * alpha_ls = e^H (A u) / e^H e.  The gradient keeps the form of eq. VarG2.
  *
- * All systems of a call iterate in lockstep on the library's single-operator
- * stencil plus batched weighted source/receiver, vector and float64 reduction
- * kernels, with the step scalars in device memory (the fused kernels assume
- * one cell per source and receiver). */
+ * All systems of a call iterate in lockstep on batched stencil, weighted
+ * source/receiver, vector and float64 reduction kernels, with the step
+ * scalars in device memory and chunks of iterations replayed from a hipGraph
+ * (the fused kernels assume one cell per source and receiver). */
 typedef struct {
   double        src[3];  /* source position (x, y, z) [m]                           */
   const double* rec;     /* HOST, 3 * n_rec receiver positions (x, y, z) [m]        */
@@ -402,8 +402,10 @@ size_t wri_offgrid_workspace_bytes(const wri_grid* grids, int32_t n_grids, const
                                    const wri_positions* pos);
 /* As wri_objective_grad, with sys[k].src and sys[k].rec replaced by pos[k]
  * (sys[k].n_rec and sys[k].d still give the data).  grad may be NULL (a solve
- * only).  flags: WRI_FLAG_UNSCALED_ALPHA; WRI_FLAG_WARM_START and
- * WRI_FLAG_ADJOINT_SOURCE are rejected, the others have no effect.  Positions
+ * only).  flags: WRI_FLAG_UNSCALED_ALPHA, WRI_FLAG_NO_GRAPH (launch every
+ * chunk of iterations eagerly instead of replaying a hipGraph captured per set
+ * of still-active systems); WRI_FLAG_WARM_START and WRI_FLAG_ADJOINT_SOURCE are
+ * rejected, the others have no effect.  Positions
  * must be finite; points outside the grid are clamped onto its boundary. */
 int wri_objective_grad_offgrid(const wri_grid* grids, int32_t n_grids, const float* const* m, const wri_system* sys,
                                int32_t n_sys, const wri_positions* pos, int32_t mode, int32_t max_iter,

@@ -15,6 +15,7 @@
 // Every reduction runs in one fixed order.
 #include "../../include/wri.h"
 #include "wri_impl.hpp"
+#include "stencil.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -46,9 +47,10 @@ struct OgSys {
   const int* scell; const double* sw;
   const int* rptr; const int* rcell; const double* rw;
   const int* uptr; const int* ucell; const int* uq; const double* uw;
+  const float* m;
   int n, ns, nr, nu;
-  int est, max_iter, pad_[2];
-  double c, lam, rtol2, omega2;
+  int est, max_iter, nx, ny, nz, nb;
+  double c, lam, rtol2, omega, omega2, h2inv, sp_scale, inv_nb;
   double2 alpha;  // KNOWN-mode weight
 };
 
@@ -79,6 +81,33 @@ __global__ void __launch_bounds__(kThreads) k_og_zero(const OgSys* __restrict__ 
   for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
     S.x[c] = make_float2(0.f, 0.f);
     S.r[c] = make_float2(0.f, 0.f);
+  }
+}
+
+// One application of A or A^H per system, with the stencil arithmetic of the
+// fused kernels (helm): which = 0: t = A p; 1: s = A^H r; 2: t = A x.  Systems
+// that stopped iterating skip (unless all).  grid = (blocks, nsys).
+__global__ void __launch_bounds__(kThreads) k_og_stencil(const OgSys* __restrict__ sy,
+                                                         const OgState* __restrict__ stv, int which, int all) {
+  const OgSys& S = sy[blockIdx.y];
+  if (!all && stv[blockIdx.y].status != kActive) return;
+  const float2* __restrict__ in = which == 0 ? S.p : (which == 1 ? S.r : S.x);
+  float2* __restrict__ out = which == 1 ? S.s : S.t;
+  const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny;
+  const double kim_sign = which == 1 ? 1.0 : -1.0;
+  const float2 zero = make_float2(0.f, 0.f);
+  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
+    const int z = c / plane, rem = c - z * plane, y = rem / nx, x = rem - y * nx;
+    const float2 cc = in[c];
+    const float2 xm = x > 0 ? in[c - 1] : zero;
+    const float2 xp = x < nx - 1 ? in[c + 1] : zero;
+    const float2 ym = y > 0 ? in[c - nx] : zero;
+    const float2 yp = y < ny - 1 ? in[c + nx] : zero;
+    const float2 zm = z > 0 ? in[c - plane] : zero;
+    const float2 zp = z < nz - 1 ? in[c + plane] : zero;
+    const double b = S.sp_scale * ((sponge_axis_d(x, nx, S.nb, S.inv_nb) + sponge_axis_d(y, ny, S.nb, S.inv_nb)) +
+                                   sponge_axis_d(z, nz, S.nb, S.inv_nb));
+    out[c] = round2(helm(cc, xm, xp, ym, yp, zm, zp, S.h2inv, S.omega2 * (double)S.m[c], kim_sign * (S.omega * b)));
   }
 }
 
@@ -565,8 +594,17 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
     S.c = (flags & WRI_FLAG_UNSCALED_ALPHA) ? 1.0 : std::sqrt(42.0) / (g.h * g.h);
     S.lam = s.lambda;
     S.rtol2 = s.rtol * s.rtol;
+    S.omega = s.omega;
     S.omega2 = s.omega * s.omega;
     S.alpha = make_double2(s.alpha.re, s.alpha.im);
+    S.m = m[s.grid];
+    S.nx = g.nx; S.ny = g.ny; S.nz = g.nz; S.nb = g.nb;
+    S.h2inv = 1.0 / (g.h * g.h);
+    if (g.nb > 0) {
+      const double d0 = 3.0 * g.v_ref * std::log(1000.0) / (2.0 * g.nb * g.h);
+      S.sp_scale = 2.0 * d0 / (g.v_ref * g.v_ref);
+      S.inv_nb = 1.0 / g.nb;
+    }
     nmax = std::max<int64_t>(nmax, n);
     rmax = std::max(rmax, S.nr);
     umax = std::max(umax, S.nu);
@@ -584,17 +622,31 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
   OG_HIP(hipStreamSynchronize(st));  // the host tables are read by the copies above
 
   const dim3 vgrid(nblk(nmax), n_sys), rgrid(nblk(rmax), n_sys), ugrid(nblk(umax), n_sys), pgrid(kParts, n_sys);
-  auto stencil = [&](int k, const float2* in, float2* out, int adjoint) -> int {
-    const wri_system& s = sys[k];
-    const wri_grid& g = grids[s.grid];
-    double sp_scale = 0.0, inv_nb = 0.0;
-    if (g.nb > 0) {
-      const double d0 = 3.0 * g.v_ref * std::log(1000.0) / (2.0 * g.nb * g.h);
-      sp_scale = 2.0 * d0 / (g.v_ref * g.v_ref);
-      inv_nb = 1.0 / g.nb;
+  // which: 0 t = A p, 1 s = A^H r, 2 t = A x (see k_og_stencil)
+  auto stencil_all = [&](hipStream_t sq, int which, int all) -> int {
+    hipLaunchKernelGGL(k_og_stencil, vgrid, dim3(kThreads), 0, sq, dsys, dst, which, all);
+    OG_HIP(hipGetLastError());
+    return WRI_OK;
+  };
+  // kCheck iterations of every system (finished systems skip inside the
+  // kernels), enqueued on stream sq
+  auto enqueue_chunk = [&](hipStream_t sq) -> int {
+    int e;
+    for (int it = 0; it < kCheck; ++it) {
+      if ((e = stencil_all(sq, 0, 0)) != WRI_OK) return e;
+      hipLaunchKernelGGL(k_og_src_sub, dim3(n_sys), dim3(64), 0, sq, dsys, dst);
+      hipLaunchKernelGGL(k_og_gather, rgrid, dim3(kThreads), 0, sq, dsys, dst);
+      hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, sq, dsys, dst, 0, 0, parts);
+      hipLaunchKernelGGL(k_og_alpha, dim3(n_sys), dim3(kThreads), 0, sq, dsys, dst, parts);
+      hipLaunchKernelGGL(k_og_update, vgrid, dim3(kThreads), 0, sq, dsys, dst);
+      OG_HIP(hipGetLastError());
+      if ((e = stencil_all(sq, 1, 0)) != WRI_OK) return e;
+      hipLaunchKernelGGL(k_og_scatter, ugrid, dim3(kThreads), 0, sq, dsys, dst, 0);
+      hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, sq, dsys, dst, 1, 0, parts);
+      hipLaunchKernelGGL(k_og_beta, dim3(n_sys), dim3(kThreads), 0, sq, dsys, dst, parts);
+      hipLaunchKernelGGL(k_og_xpby, vgrid, dim3(kThreads), 0, sq, dsys, dst);
+      OG_HIP(hipGetLastError());
     }
-    OG_HIP(launch_apply(g.nx, g.ny, g.nz, g.nb, 1.0 / (g.h * g.h), sp_scale, inv_nb, s.omega, m[s.grid], in, out,
-                        adjoint, -1, make_double2(0.0, 0.0), st));
     return WRI_OK;
   };
   // set-up: x = 0, r = b, s = S^H b
@@ -602,8 +654,7 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
   OG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_og_init, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst);
   OG_HIP(hipGetLastError());
-  for (int k = 0; k < n_sys; ++k)
-    if ((rc = stencil(k, hs[k].r, hs[k].s, 1)) != WRI_OK) return rc;
+  if ((rc = stencil_all(st, 1, 1)) != WRI_OK) return rc;
   hipLaunchKernelGGL(k_og_scatter, ugrid, dim3(kThreads), 0, st, dsys, dst, 1);
   hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 1, 1, parts);
   hipLaunchKernelGGL(k_og_start, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
@@ -616,38 +667,66 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
     return WRI_OK;
   };
   if ((rc = read()) != WRI_OK) return rc;
+  // A chunk of kCheck iterations is captured once into a hipGraph (kernel
+  // nodes only) and replayed on the caller's stream; the graph lives for this
+  // call only (it holds this workspace's pointers).
+  hipStream_t cs = nullptr;
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  auto release = [&]() {
+    for (auto& kv : graphs) {
+      (void)hipGraphExecDestroy(kv.second.second);
+      (void)hipGraphDestroy(kv.second.first);
+    }
+    graphs.clear();
+    if (cs != nullptr) (void)hipStreamDestroy(cs);
+    cs = nullptr;
+  };
+  auto run_chunk = [&]() -> int {
+    auto it = graphs.find(0);
+    if (it == graphs.end()) {
+      if (cs == nullptr) OG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      OG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      const int e = enqueue_chunk(cs);
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(cs, &graph);
+      if (e != WRI_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return e;
+      }
+      if (ec != hipSuccess) return report_error(WRI_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return report_error(WRI_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+      }
+      it = graphs.emplace(0, std::make_pair(graph, exec)).first;
+    }
+    OG_HIP(hipGraphLaunch(it->second.second, st));
+    return WRI_OK;
+  };
   std::vector<int> active;
   for (int64_t done = 0;; done += kCheck) {
     active.clear();
     for (int k = 0; k < n_sys; ++k)
       if (hst[k].status == kActive) active.push_back(k);
     if (active.empty()) break;
-    if (done > (int64_t)max_iter + kCheck) return report_error(WRI_EHIP, "internal: systems active past max_iter");
-    for (int it = 0; it < kCheck; ++it) {
-      for (int k : active)
-        if ((rc = stencil(k, hs[k].p, hs[k].t, 0)) != WRI_OK) return rc;
-      hipLaunchKernelGGL(k_og_src_sub, dim3(n_sys), dim3(64), 0, st, dsys, dst);
-      hipLaunchKernelGGL(k_og_gather, rgrid, dim3(kThreads), 0, st, dsys, dst);
-      hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 0, 0, parts);
-      hipLaunchKernelGGL(k_og_alpha, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
-      hipLaunchKernelGGL(k_og_update, vgrid, dim3(kThreads), 0, st, dsys, dst);
-      OG_HIP(hipGetLastError());
-      for (int k : active)
-        if ((rc = stencil(k, hs[k].r, hs[k].s, 1)) != WRI_OK) return rc;
-      hipLaunchKernelGGL(k_og_scatter, ugrid, dim3(kThreads), 0, st, dsys, dst, 0);
-      hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 1, 0, parts);
-      hipLaunchKernelGGL(k_og_beta, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
-      hipLaunchKernelGGL(k_og_xpby, vgrid, dim3(kThreads), 0, st, dsys, dst);
-      OG_HIP(hipGetLastError());
+    if (done > (int64_t)max_iter + kCheck) {
+      release();
+      return report_error(WRI_EHIP, "internal: systems active past max_iter");
     }
-    if ((rc = read()) != WRI_OK) return rc;
+    rc = (flags & WRI_FLAG_NO_GRAPH) ? enqueue_chunk(st) : run_chunk();
+    if (rc == WRI_OK) rc = read();
+    if (rc != WRI_OK) {
+      release();
+      return rc;
+    }
   }
+  release();
   // objective, source weights, gradient
   hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 2, 1, parts);
   OG_HIP(hipGetLastError());
-  if (mode == WRI_ESTIMATE)
-    for (int k = 0; k < n_sys; ++k)
-      if ((rc = stencil(k, hs[k].x, hs[k].t, 0)) != WRI_OK) return rc;
+  if (mode == WRI_ESTIMATE && (rc = stencil_all(st, 2, 1)) != WRI_OK) return rc;
   hipLaunchKernelGGL(k_og_final, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
   OG_HIP(hipGetLastError());
   if (grad != nullptr)
