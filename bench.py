@@ -45,17 +45,17 @@ BYTES_NOTE = {"fwd": "36, +24 on even iterations (x update of two steps)", "adj"
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "b4cb90702adbf97b",
+    "sources_sha256": "02ef96444f5e3fa8",
     "tiles": {
-        "8,1,32,1,4": {"fwd_x": {"fetch_kib": 1844788.1, "write_kib": 2359536.5},
-                       "fwd": {"fetch_kib": 1029700.1, "write_kib": 1573055.5},
-                       "adj": {"fetch_kib": 1011438.7, "write_kib": 1573100.0}},
-        "8,1,32,1,0": {"fwd_x": {"fetch_kib": 2018144.9, "write_kib": 2359560.8},
-                       "fwd": {"fetch_kib": 1201010.1, "write_kib": 1573086.4},
-                       "adj": {"fetch_kib": 1185935.4, "write_kib": 1573104.1}},
-        "4,2,32,1,0": {"fwd_x": {"fetch_kib": 2060307.0, "write_kib": 2359674.6},
-                       "fwd": {"fetch_kib": 1224300.9, "write_kib": 1573148.4},
-                       "adj": {"fetch_kib": 1245184.7, "write_kib": 1573206.4}},
+        "8,1,32,1,4": {"fwd_x": {"fetch_kib": 1844253.8, "write_kib": 2359535.0},
+                       "fwd": {"fetch_kib": 1031510.2, "write_kib": 1573056.4},
+                       "adj": {"fetch_kib": 1010905.1, "write_kib": 1573099.3}},
+        "8,1,32,1,0": {"fwd_x": {"fetch_kib": 2018107.5, "write_kib": 2359560.2},
+                       "fwd": {"fetch_kib": 1199048.2, "write_kib": 1573086.1},
+                       "adj": {"fetch_kib": 1184879.9, "write_kib": 1573104.8}},
+        "4,2,32,1,0": {"fwd_x": {"fetch_kib": 2059830.9, "write_kib": 2359677.1},
+                       "fwd": {"fetch_kib": 1223818.1, "write_kib": 1573144.6},
+                       "adj": {"fetch_kib": 1245130.3, "write_kib": 1573206.2}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
