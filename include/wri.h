@@ -388,10 +388,11 @@ int wri_objective_grad_model(const wri_grid* model_grid, const float* m_model, c
  * -c e and the least-squares weight of the result is
  * alpha_ls = e^H (A u) / e^H e.  The gradient keeps the form of eq. VarG2.
  *
- * All systems of a call iterate in lockstep on batched stencil, weighted
- * source/receiver, vector and float64 reduction kernels, with the step
- * scalars in device memory and chunks of iterations replayed from a hipGraph
- * (the fused kernels assume one cell per source and receiver). */
+ * All systems of a call iterate in lockstep, four launches per iteration
+ * (forward pass, source/receiver rows and step, adjoint pass, rows and
+ * beta), with the step scalars in device memory and chunks of iterations
+ * replayed from a hipGraph (the fused kernels assume one cell per source and
+ * receiver). */
 typedef struct {
   double        src[3];  /* source position (x, y, z) [m]                           */
   const double* rec;     /* HOST, 3 * n_rec receiver positions (x, y, z) [m]        */

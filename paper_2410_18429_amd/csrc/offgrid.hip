@@ -2,11 +2,13 @@
 // receiver sampling P of eqs. ObjPen / SimpObj become trilinear interpolation
 // weights over up to 8 cells each, and the same CGLS (the reading of
 // Algorithm 1 used throughout the library) runs for all systems of a call in
-// lockstep: the library's single-operator stencil for A and A^H, and batched
-// kernels (one block row per system) for the weighted source and receiver
-// terms, the vector updates and the float64 reductions.  Step scalars live in
-// device memory; the host checks the statuses every kCheck iterations and
-// stops launching the stencils of finished systems.
+// lockstep, four launches per iteration: a forward pass (p update and
+// t = A p at each cell from its neighbours' recomputed p), a one-block-per-
+// system pass for the source column, P p and the step a, an adjoint pass
+// (r update, s = A^H r, x update) and a one-block-per-system pass for P^H r2,
+// the source row and beta.  The stencil arithmetic is the fused kernels'
+// (stencil.hpp); step scalars live in device memory; chunks of iterations
+// replay from a hipGraph and the host checks the statuses between them.
 //
 // P p: one thread per receiver sums its weighted cells (reads only).  P^H r2:
 // a gather over the distinct receiver cells of a system (each cell's list of
@@ -37,12 +39,13 @@ size_t al(size_t v) { return (v + kAl - 1) / kAl * kAl; }
 
 int nblk(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 4096)); }
 
-constexpr int kParts = 128;  // partial sums per system and reduction
+constexpr int kParts = 128;  // blocks (and partial sums) per system in the stencil passes
 constexpr int kCheck = 32;   // iterations between host checks of the statuses
 
-// One system, resident in the workspace.
+// One system, resident in the workspace.  r and p are ping-pong pairs (the
+// stencil passes read neighbours of the old vector while writing the new one).
 struct OgSys {
-  float2 *x, *r, *p, *s, *t, *r2, *t2;
+  float2 *x, *r[2], *p[2], *s, *t, *r2, *t2;
   const float2* d;
   const int* scell; const double* sw;
   const int* rptr; const int* rcell; const double* rw;
@@ -54,7 +57,8 @@ struct OgSys {
   double2 alpha;  // KNOWN-mode weight
 };
 
-// Mutable scalars of one system (float64).
+// Mutable scalars of one system (float64).  iters = k while iteration k runs:
+// p_k is in p[k & 1], r_k in r[k & 1].
 struct OgState {
   double gamma, gamma0, a, beta, J;
   double2 xa, pa, sa, eau;
@@ -74,49 +78,50 @@ __device__ __forceinline__ double bsum(double v, double* red) {  // all threads 
 }
 
 __device__ __forceinline__ float2 f2d(double a, double b) { return make_float2((float)a, (float)b); }
+__device__ __forceinline__ double nrm(float2 v) { return (double)v.x * v.x + (double)v.y * v.y; }
+// y + a x in float64, rounded once: the value every neighbour recomputes identically
+__device__ __forceinline__ float2 axpyd(float2 y, double a, float2 x) {
+  return f2d((double)y.x + a * (double)x.x, (double)y.y + a * (double)x.y);
+}
 
-// x = 0, r = 0 (grid (blocks, nsys))
+__device__ __forceinline__ double sponge_at(const OgSys& S, int x, int y, int z) {
+  return S.sp_scale * ((sponge_axis_d(x, S.nx, S.nb, S.inv_nb) + sponge_axis_d(y, S.ny, S.nb, S.inv_nb)) +
+                       sponge_axis_d(z, S.nz, S.nb, S.inv_nb));
+}
+
+// x = 0, r_0 = 0, p_{-1} = 0 (grid (blocks, nsys))
 __global__ void __launch_bounds__(kThreads) k_og_zero(const OgSys* __restrict__ sy) {
   const OgSys& S = sy[blockIdx.y];
+  const float2 z = make_float2(0.f, 0.f);
   for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
-    S.x[c] = make_float2(0.f, 0.f);
-    S.r[c] = make_float2(0.f, 0.f);
+    S.x[c] = z;
+    S.r[0][c] = z;
+    S.p[1][c] = z;
   }
 }
 
-// One application of A or A^H per system, with the stencil arithmetic of the
-// fused kernels (helm): which = 0: t = A p; 1: s = A^H r; 2: t = A x.  Systems
-// that stopped iterating skip (unless all).  grid = (blocks, nsys).
-__global__ void __launch_bounds__(kThreads) k_og_stencil(const OgSys* __restrict__ sy,
-                                                         const OgState* __restrict__ stv, int which, int all) {
+// t = A x (the least-squares source weight of the result)  (grid (blocks, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_ax(const OgSys* __restrict__ sy) {
   const OgSys& S = sy[blockIdx.y];
-  if (!all && stv[blockIdx.y].status != kActive) return;
-  const float2* __restrict__ in = which == 0 ? S.p : (which == 1 ? S.r : S.x);
-  float2* __restrict__ out = which == 1 ? S.s : S.t;
   const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny;
-  const double kim_sign = which == 1 ? 1.0 : -1.0;
   const float2 zero = make_float2(0.f, 0.f);
+  const float2* __restrict__ in = S.x;
   for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
     const int z = c / plane, rem = c - z * plane, y = rem / nx, x = rem - y * nx;
-    const float2 cc = in[c];
-    const float2 xm = x > 0 ? in[c - 1] : zero;
-    const float2 xp = x < nx - 1 ? in[c + 1] : zero;
-    const float2 ym = y > 0 ? in[c - nx] : zero;
-    const float2 yp = y < ny - 1 ? in[c + nx] : zero;
-    const float2 zm = z > 0 ? in[c - plane] : zero;
-    const float2 zp = z < nz - 1 ? in[c + plane] : zero;
-    const double b = S.sp_scale * ((sponge_axis_d(x, nx, S.nb, S.inv_nb) + sponge_axis_d(y, ny, S.nb, S.inv_nb)) +
-                                   sponge_axis_d(z, nz, S.nb, S.inv_nb));
-    out[c] = round2(helm(cc, xm, xp, ym, yp, zm, zp, S.h2inv, S.omega2 * (double)S.m[c], kim_sign * (S.omega * b)));
+    const float2 xm = x > 0 ? in[c - 1] : zero, xp = x < nx - 1 ? in[c + 1] : zero;
+    const float2 ym = y > 0 ? in[c - nx] : zero, yp = y < ny - 1 ? in[c + nx] : zero;
+    const float2 zm = z > 0 ? in[c - plane] : zero, zp = z < nz - 1 ? in[c + plane] : zero;
+    S.t[c] = round2(helm(in[c], xm, xp, ym, yp, zm, zp, S.h2inv, S.omega2 * (double)S.m[c],
+                         -(S.omega * sponge_at(S, x, y, z))));
   }
 }
 
-// r[src] = alpha e (KNOWN), r2 = lam d, state reset (grid nsys)
+// r_0[src] = alpha e (KNOWN), r2 = lam d, state reset (grid nsys)
 __global__ void __launch_bounds__(kThreads) k_og_init(const OgSys* __restrict__ sy, OgState* __restrict__ stv) {
   const OgSys& S = sy[blockIdx.x];
   if (!S.est && (int)threadIdx.x < S.ns) {
     const double w = S.sw[threadIdx.x];
-    S.r[S.scell[threadIdx.x]] = f2d(S.alpha.x * w, S.alpha.y * w);
+    S.r[0][S.scell[threadIdx.x]] = f2d(S.alpha.x * w, S.alpha.y * w);
   }
   for (int q = threadIdx.x; q < S.nr; q += kThreads)
     S.r2[q] = f2d(S.lam * (double)S.d[q].x, S.lam * (double)S.d[q].y);
@@ -127,122 +132,79 @@ __global__ void __launch_bounds__(kThreads) k_og_init(const OgSys* __restrict__ 
   }
 }
 
-// t[src] -= c pa w  (grid nsys)
-__global__ void __launch_bounds__(64) k_og_src_sub(const OgSys* __restrict__ sy, const OgState* __restrict__ stv) {
-  const OgSys& S = sy[blockIdx.x];
-  const OgState& T = stv[blockIdx.x];
-  if (T.status != kActive || !S.est || (int)threadIdx.x >= S.ns) return;
-  const int c = S.scell[threadIdx.x];
-  const double w = S.sw[threadIdx.x];
-  const float2 v = S.t[c];
-  S.t[c] = f2d((double)v.x - S.c * T.pa.x * w, (double)v.y - S.c * T.pa.y * w);
-}
-
-// t2 = lam P p  (grid (blocks, nsys))
-__global__ void __launch_bounds__(kThreads) k_og_gather(const OgSys* __restrict__ sy,
-                                                        const OgState* __restrict__ stv) {
-  const OgSys& S = sy[blockIdx.y];
-  if (stv[blockIdx.y].status != kActive) return;
-  const int q = blockIdx.x * kThreads + threadIdx.x;
-  if (q >= S.nr) return;
-  double re = 0.0, im = 0.0;
-  for (int j = S.rptr[q]; j < S.rptr[q + 1]; ++j) {
-    const float2 v = S.p[S.rcell[j]];
-    re += S.rw[j] * (double)v.x;
-    im += S.rw[j] * (double)v.y;
-  }
-  S.t2[q] = f2d(S.lam * re, S.lam * im);
-}
-
-// s[u] += lam sum_j w_j r2[q_j] over the distinct receiver cells  (grid (blocks, nsys))
-__global__ void __launch_bounds__(kThreads) k_og_scatter(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
-                                                         int all) {
-  const OgSys& S = sy[blockIdx.y];
-  if (!all && stv[blockIdx.y].status != kActive) return;
-  const int u = blockIdx.x * kThreads + threadIdx.x;
-  if (u >= S.nu) return;
-  double re = 0.0, im = 0.0;
-  for (int j = S.uptr[u]; j < S.uptr[u + 1]; ++j) {
-    const float2 v = S.r2[S.uq[j]];
-    re += S.uw[j] * (double)v.x;
-    im += S.uw[j] * (double)v.y;
-  }
-  const int c = S.ucell[u];
-  const float2 v = S.s[c];
-  S.s[c] = f2d((double)v.x + S.lam * re, (double)v.y + S.lam * im);
-}
-
-// per-system partial sums of |v|^2, v = t (which 0), s (1) or r (2)  (grid (kParts, nsys))
-__global__ void __launch_bounds__(kThreads) k_og_norm(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
-                                                      int which, int all, double* __restrict__ parts) {
+// Forward pass of iteration k: p_k = s_k + beta p_{k-1} (computed at the cell
+// and its six neighbours), t = A p_k, per-block partials of ||t||^2 (the
+// source-column term is added by k_og_alpha).  grid (kParts, nsys).
+__global__ void __launch_bounds__(kThreads) k_og_fwd(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
+                                                     double* __restrict__ parts) {
   __shared__ double red[kThreads / 64];
   const OgSys& S = sy[blockIdx.y];
-  const bool on = all || stv[blockIdx.y].status == kActive;  // uniform over the block
-  const float2* v = which == 0 ? S.t : (which == 1 ? S.s : S.r);
+  const OgState& T = stv[blockIdx.y];
   double acc = 0.0;
-  if (on)
+  if (T.status == kActive) {  // uniform over the block
+    const int k = T.iters;
+    const float2* __restrict__ sv = S.s;
+    const float2* __restrict__ po = S.p[(k + 1) & 1];
+    float2* __restrict__ pn = S.p[k & 1];
+    const double beta = T.beta;
+    const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny;
+    const float2 zero = make_float2(0.f, 0.f);
     for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += kParts * kThreads) {
-      const float2 x = v[c];
-      acc += (double)x.x * x.x + (double)x.y * x.y;
+      const int z = c / plane, rem = c - z * plane, y = rem / nx, x = rem - y * nx;
+      const float2 pc = axpyd(sv[c], beta, po[c]);
+      const float2 xm = x > 0 ? axpyd(sv[c - 1], beta, po[c - 1]) : zero;
+      const float2 xp = x < nx - 1 ? axpyd(sv[c + 1], beta, po[c + 1]) : zero;
+      const float2 ym = y > 0 ? axpyd(sv[c - nx], beta, po[c - nx]) : zero;
+      const float2 yp = y < ny - 1 ? axpyd(sv[c + nx], beta, po[c + nx]) : zero;
+      const float2 zm = z > 0 ? axpyd(sv[c - plane], beta, po[c - plane]) : zero;
+      const float2 zp = z < nz - 1 ? axpyd(sv[c + plane], beta, po[c + plane]) : zero;
+      pn[c] = pc;
+      const float2 tv = round2(helm(pc, xm, xp, ym, yp, zm, zp, S.h2inv, S.omega2 * (double)S.m[c],
+                                    -(S.omega * sponge_at(S, x, y, z))));
+      S.t[c] = tv;
+      acc += nrm(tv);
     }
+  }
   acc = bsum(acc, red);
   if (threadIdx.x == 0) parts[blockIdx.y * kParts + blockIdx.x] = acc;
 }
 
-// gamma0 = ||S^H b||^2 after the set-up pass: p_a = s_a, statuses  (grid nsys)
-__global__ void __launch_bounds__(kThreads) k_og_start(const OgSys* __restrict__ sy, OgState* __restrict__ stv,
-                                                       const double* __restrict__ parts) {
-  __shared__ double red[kThreads / 64];
-  const OgSys& S = sy[blockIdx.x];
-  OgState& T = stv[blockIdx.x];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
-  v = bsum(v, red);
-  double sr = 0.0, si = 0.0;
-  if (S.est)
-    for (int i = 0; i < S.ns; ++i) {
-      const float2 x = S.r[S.scell[i]];
-      sr -= S.c * S.sw[i] * (double)x.x;
-      si -= S.c * S.sw[i] * (double)x.y;
-    }
-  if (threadIdx.x == 0) {
-    const double g = v + sr * sr + si * si;
-    T.gamma = T.gamma0 = g;
-    T.sa = T.pa = make_double2(sr, si);
-    if (g == 0.0) T.status = kZeroRhs;
-    else if (g <= S.rtol2 * g) T.status = kConverged;
-    else if (S.max_iter <= 0) T.status = kMaxIter;
-  }
-}
-
-// p = s (grid (blocks, nsys))
-__global__ void __launch_bounds__(kThreads) k_og_copy_ps(const OgSys* __restrict__ sy) {
-  const OgSys& S = sy[blockIdx.y];
-  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) S.p[c] = S.s[c];
-}
-
-// delta = ||t||^2 + ||t2||^2, a = gamma / delta, x_a += a p_a, r2 -= a t2  (grid nsys)
+// delta = ||t||^2 with the source column (t[src] -= c p_a w) + ||t2||^2 with
+// t2 = lam P p_k; a = gamma / delta; x_a += a p_a; r2 -= a t2  (grid nsys)
 __global__ void __launch_bounds__(kThreads) k_og_alpha(const OgSys* __restrict__ sy, OgState* __restrict__ stv,
                                                        const double* __restrict__ parts) {
   __shared__ double red[kThreads / 64];
   const OgSys& S = sy[blockIdx.x];
   OgState& T = stv[blockIdx.x];
   if (T.status != kActive) return;  // uniform over the block
+  const float2* __restrict__ pk = S.p[T.iters & 1];
   double v = 0.0;
   for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
+  if (S.est && (int)threadIdx.x < S.ns) {  // distinct source cells, one per thread
+    const int c = S.scell[threadIdx.x];
+    const double w = S.sw[threadIdx.x];
+    const float2 t0 = S.t[c];
+    const float2 t1 = f2d((double)t0.x - S.c * T.pa.x * w, (double)t0.y - S.c * T.pa.y * w);
+    S.t[c] = t1;
+    v += nrm(t1) - nrm(t0);
+  }
   for (int q = threadIdx.x; q < S.nr; q += kThreads) {
-    const float2 x = S.t2[q];
-    v += (double)x.x * x.x + (double)x.y * x.y;
+    double re = 0.0, im = 0.0;
+    for (int j = S.rptr[q]; j < S.rptr[q + 1]; ++j) {
+      const float2 x = pk[S.rcell[j]];
+      re += S.rw[j] * (double)x.x;
+      im += S.rw[j] * (double)x.y;
+    }
+    const float2 t2 = f2d(S.lam * re, S.lam * im);
+    S.t2[q] = t2;
+    v += nrm(t2);
   }
   const double delta = bsum(v, red);
   const double gamma = T.gamma;
   const bool bad = !(delta > 0.0) || !isfinite(delta) || !isfinite(gamma);
   const double a = bad ? 0.0 : gamma / delta;
   if (!bad)
-    for (int q = threadIdx.x; q < S.nr; q += kThreads) {
-      const float2 r = S.r2[q], t = S.t2[q];
-      S.r2[q] = f2d((double)r.x - a * t.x, (double)r.y - a * t.y);
-    }
+    for (int q = threadIdx.x; q < S.nr; q += kThreads) S.r2[q] = axpyd(S.r2[q], -a, S.t2[q]);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (bad) {
@@ -254,44 +216,117 @@ __global__ void __launch_bounds__(kThreads) k_og_alpha(const OgSys* __restrict__
   }
 }
 
-// x += a p, r -= a t  (grid (blocks, nsys))
-__global__ void __launch_bounds__(kThreads) k_og_update(const OgSys* __restrict__ sy,
-                                                        const OgState* __restrict__ stv) {
+// Adjoint pass: r_{k+1} = r_k - a t (at the cell and its six neighbours),
+// s = A^H r_{k+1}, x += a p_k, per-block partials of ||s||^2 (the receiver
+// rows are added by k_og_beta).  setup = 1: the pass on r_0 with no update
+// (s_0 = A^H r_0, copied r_0 into r_1).  grid (kParts, nsys).
+__global__ void __launch_bounds__(kThreads) k_og_adj(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
+                                                     double* __restrict__ parts, int setup) {
+  __shared__ double red[kThreads / 64];
   const OgSys& S = sy[blockIdx.y];
   const OgState& T = stv[blockIdx.y];
-  if (T.status != kActive) return;
-  const double a = T.a;
-  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
-    const float2 x = S.x[c], p = S.p[c], r = S.r[c], t = S.t[c];
-    S.x[c] = f2d((double)x.x + a * p.x, (double)x.y + a * p.y);
-    S.r[c] = f2d((double)r.x - a * t.x, (double)r.y - a * t.y);
+  double acc = 0.0;
+  if (setup || T.status == kActive) {  // uniform over the block
+    const int k = setup ? 0 : T.iters;
+    const double a = setup ? 0.0 : T.a;
+    const float2* __restrict__ ro = S.r[k & 1];
+    float2* __restrict__ rn = S.r[(k + 1) & 1];
+    const float2* __restrict__ tv = S.t;
+    const float2* __restrict__ pk = S.p[k & 1];
+    const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny;
+    const float2 zero = make_float2(0.f, 0.f);
+    auto rnew = [&](int c) { return setup ? ro[c] : axpyd(ro[c], -a, tv[c]); };
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += kParts * kThreads) {
+      const int z = c / plane, rem = c - z * plane, y = rem / nx, x = rem - y * nx;
+      const float2 rc = rnew(c);
+      const float2 xm = x > 0 ? rnew(c - 1) : zero;
+      const float2 xp = x < nx - 1 ? rnew(c + 1) : zero;
+      const float2 ym = y > 0 ? rnew(c - nx) : zero;
+      const float2 yp = y < ny - 1 ? rnew(c + nx) : zero;
+      const float2 zm = z > 0 ? rnew(c - plane) : zero;
+      const float2 zp = z < nz - 1 ? rnew(c + plane) : zero;
+      rn[c] = rc;
+      const float2 sv = round2(helm(rc, xm, xp, ym, yp, zm, zp, S.h2inv, S.omega2 * (double)S.m[c],
+                                    S.omega * sponge_at(S, x, y, z)));
+      S.s[c] = sv;
+      acc += nrm(sv);
+      if (!setup) S.x[c] = axpyd(S.x[c], a, pk[c]);
+    }
+  }
+  acc = bsum(acc, red);
+  if (threadIdx.x == 0) parts[blockIdx.y * kParts + blockIdx.x] = acc;
+}
+
+// The receiver rows of S^H r (s += lam P^H r2 over the distinct receiver
+// cells) and the source row s_a = -c e^H r, with gamma = ||s||^2 + |s_a|^2:
+// shared by the set-up (gamma0) and every iteration (beta, statuses).
+__device__ void og_finish_s(const OgSys& S, const float2* __restrict__ r, double pv, double* red, double* gs,
+                            double2* sa) {
+  double v = pv;
+  for (int u = threadIdx.x; u < S.nu; u += kThreads) {
+    double re = 0.0, im = 0.0;
+    for (int j = S.uptr[u]; j < S.uptr[u + 1]; ++j) {
+      const float2 x = S.r2[S.uq[j]];
+      re += S.uw[j] * (double)x.x;
+      im += S.uw[j] * (double)x.y;
+    }
+    const int c = S.ucell[u];
+    const float2 s0 = S.s[c];
+    const float2 s1 = f2d((double)s0.x + S.lam * re, (double)s0.y + S.lam * im);
+    S.s[c] = s1;
+    v += nrm(s1) - nrm(s0);
+  }
+  v = bsum(v, red);
+  double sr = 0.0, si = 0.0;
+  if (S.est)
+    for (int i = 0; i < S.ns; ++i) {
+      const float2 x = r[S.scell[i]];
+      sr -= S.c * S.sw[i] * (double)x.x;
+      si -= S.c * S.sw[i] * (double)x.y;
+    }
+  *gs = v + sr * sr + si * si;
+  *sa = make_double2(sr, si);
+}
+
+// gamma0 = ||S^H b||^2 after the set-up pass; p_a = s_a, beta = 0 (p_{-1} = 0)  (grid nsys)
+__global__ void __launch_bounds__(kThreads) k_og_start(const OgSys* __restrict__ sy, OgState* __restrict__ stv,
+                                                       const double* __restrict__ parts) {
+  __shared__ double red[kThreads / 64];
+  const OgSys& S = sy[blockIdx.x];
+  OgState& T = stv[blockIdx.x];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
+  double g;
+  double2 sa;
+  og_finish_s(S, S.r[0], v, red, &g, &sa);
+  if (threadIdx.x == 0) {
+    T.gamma = T.gamma0 = g;
+    T.sa = T.pa = sa;
+    T.beta = 0.0;
+    if (g == 0.0) T.status = kZeroRhs;
+    else if (g <= S.rtol2 * g) T.status = kConverged;
+    else if (S.max_iter <= 0) T.status = kMaxIter;
   }
 }
 
-// s_a = -c e^H r, gamma' = ||s||^2 + |s_a|^2, beta, statuses, p_a  (grid nsys)
+// s_{k+1} completed, gamma' , beta, statuses, p_a; iteration k done  (grid nsys)
 __global__ void __launch_bounds__(kThreads) k_og_beta(const OgSys* __restrict__ sy, OgState* __restrict__ stv,
                                                       const double* __restrict__ parts) {
   __shared__ double red[kThreads / 64];
   const OgSys& S = sy[blockIdx.x];
   OgState& T = stv[blockIdx.x];
-  if (T.status != kActive) return;
+  if (T.status != kActive) return;  // uniform over the block
   double v = 0.0;
   for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
-  v = bsum(v, red);
+  double gnew;
+  double2 sa;
+  og_finish_s(S, S.r[(T.iters + 1) & 1], v, red, &gnew, &sa);
   if (threadIdx.x == 0) {
-    double sr = 0.0, si = 0.0;
-    if (S.est)
-      for (int i = 0; i < S.ns; ++i) {
-        const float2 x = S.r[S.scell[i]];
-        sr -= S.c * S.sw[i] * (double)x.x;
-        si -= S.c * S.sw[i] * (double)x.y;
-      }
-    const double gnew = v + sr * sr + si * si;
     const double beta = gnew / T.gamma;
     T.beta = beta;
     T.gamma = gnew;
-    T.sa = make_double2(sr, si);
-    T.pa = make_double2(sr + beta * T.pa.x, si + beta * T.pa.y);
+    T.sa = sa;
+    T.pa = make_double2(sa.x + beta * T.pa.x, sa.y + beta * T.pa.y);
     T.iters += 1;
     if (gnew <= S.rtol2 * T.gamma0) T.status = kConverged;
     else if (!isfinite(gnew)) T.status = kBreakdown;
@@ -299,16 +334,16 @@ __global__ void __launch_bounds__(kThreads) k_og_beta(const OgSys* __restrict__ 
   }
 }
 
-// p = s + beta p  (grid (blocks, nsys))
-__global__ void __launch_bounds__(kThreads) k_og_xpby(const OgSys* __restrict__ sy, const OgState* __restrict__ stv) {
+// per-system partials of ||r||^2 for the final residual r[iters & 1]  (grid (kParts, nsys))
+__global__ void __launch_bounds__(kThreads) k_og_rnorm(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
+                                                       double* __restrict__ parts) {
+  __shared__ double red[kThreads / 64];
   const OgSys& S = sy[blockIdx.y];
-  const OgState& T = stv[blockIdx.y];
-  if (T.status != kActive) return;
-  const double b = T.beta;
-  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += gridDim.x * kThreads) {
-    const float2 s = S.s[c], p = S.p[c];
-    S.p[c] = f2d((double)s.x + b * p.x, (double)s.y + b * p.y);
-  }
+  const float2* __restrict__ r = S.r[stv[blockIdx.y].iters & 1];
+  double acc = 0.0;
+  for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += kParts * kThreads) acc += nrm(r[c]);
+  acc = bsum(acc, red);
+  if (threadIdx.x == 0) parts[blockIdx.y * kParts + blockIdx.x] = acc;
 }
 
 // J = ||r||^2 + ||r2||^2; e^H (A u) from t = A x  (grid nsys)
@@ -319,10 +354,7 @@ __global__ void __launch_bounds__(kThreads) k_og_final(const OgSys* __restrict__
   OgState& T = stv[blockIdx.x];
   double v = 0.0;
   for (int i = threadIdx.x; i < kParts; i += kThreads) v += parts[blockIdx.x * kParts + i];
-  for (int q = threadIdx.x; q < S.nr; q += kThreads) {
-    const float2 x = S.r2[q];
-    v += (double)x.x * x.x + (double)x.y * x.y;
-  }
+  for (int q = threadIdx.x; q < S.nr; q += kThreads) v += nrm(S.r2[q]);
   v = bsum(v, red);
   if (threadIdx.x == 0) {
     T.J = v;
@@ -347,7 +379,7 @@ __global__ void __launch_bounds__(kThreads) k_og_grad(const OgSys* __restrict__ 
       const int i = idx[j];
       if (stv[i].status == kBreakdown) continue;
       const OgSys& S = sy[i];
-      const float2 a = S.x[c], b = S.r[c];
+      const float2 a = S.x[c], b = S.r[stv[i].iters & 1][c];
       acc -= 2.0 * S.omega2 * ((double)a.x * b.x + (double)a.y * b.y);
     }
     g[c] = (float)acc;
@@ -514,7 +546,7 @@ int og_layout(const wri_grid* grids, const wri_system* sys, int n_sys, std::vect
   L->vec.resize(n_sys);
   L->rvec.resize(n_sys);
   for (int k = 0; k < n_sys; ++k) {
-    L->vec[k] = take(5 * al(sizeof(float2) * (size_t)ncell(grids[sys[k].grid])));
+    L->vec[k] = take(7 * al(sizeof(float2) * (size_t)ncell(grids[sys[k].grid])));
     L->rvec[k] = take(2 * al(sizeof(float2) * (size_t)sys[k].n_rec));
   }
   L->sys = take(sizeof(OgSys) * (size_t)std::max(n_sys, 1));
@@ -575,10 +607,12 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
     OgSys& S = hs[k];
     S = OgSys{};
     S.x = (u_out != nullptr && u_out[k] != nullptr) ? reinterpret_cast<float2*>(u_out[k]) : v;
-    S.r = reinterpret_cast<float2*>(base + L.vec[k] + vb);
-    S.p = reinterpret_cast<float2*>(base + L.vec[k] + 2 * vb);
-    S.s = reinterpret_cast<float2*>(base + L.vec[k] + 3 * vb);
-    S.t = reinterpret_cast<float2*>(base + L.vec[k] + 4 * vb);
+    S.r[0] = reinterpret_cast<float2*>(base + L.vec[k] + vb);
+    S.r[1] = reinterpret_cast<float2*>(base + L.vec[k] + 2 * vb);
+    S.p[0] = reinterpret_cast<float2*>(base + L.vec[k] + 3 * vb);
+    S.p[1] = reinterpret_cast<float2*>(base + L.vec[k] + 4 * vb);
+    S.s = reinterpret_cast<float2*>(base + L.vec[k] + 5 * vb);
+    S.t = reinterpret_cast<float2*>(base + L.vec[k] + 6 * vb);
     S.r2 = reinterpret_cast<float2*>(base + L.rvec[k]);
     S.t2 = reinterpret_cast<float2*>(base + L.rvec[k] + rb);
     S.d = reinterpret_cast<const float2*>(s.d);
@@ -621,44 +655,26 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
   OG_HIP(hipMemcpyAsync(didx, order.data(), sizeof(int) * n_sys, hipMemcpyHostToDevice, st));
   OG_HIP(hipStreamSynchronize(st));  // the host tables are read by the copies above
 
-  const dim3 vgrid(nblk(nmax), n_sys), rgrid(nblk(rmax), n_sys), ugrid(nblk(umax), n_sys), pgrid(kParts, n_sys);
-  // which: 0 t = A p, 1 s = A^H r, 2 t = A x (see k_og_stencil)
-  auto stencil_all = [&](hipStream_t sq, int which, int all) -> int {
-    hipLaunchKernelGGL(k_og_stencil, vgrid, dim3(kThreads), 0, sq, dsys, dst, which, all);
-    OG_HIP(hipGetLastError());
-    return WRI_OK;
-  };
+  const dim3 vgrid(nblk(nmax), n_sys), pgrid(kParts, n_sys);
+  (void)rmax;
+  (void)umax;
   // kCheck iterations of every system (finished systems skip inside the
-  // kernels), enqueued on stream sq
+  // kernels), enqueued on stream sq: four launches per iteration
   auto enqueue_chunk = [&](hipStream_t sq) -> int {
-    int e;
     for (int it = 0; it < kCheck; ++it) {
-      if ((e = stencil_all(sq, 0, 0)) != WRI_OK) return e;
-      hipLaunchKernelGGL(k_og_src_sub, dim3(n_sys), dim3(64), 0, sq, dsys, dst);
-      hipLaunchKernelGGL(k_og_gather, rgrid, dim3(kThreads), 0, sq, dsys, dst);
-      hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, sq, dsys, dst, 0, 0, parts);
+      hipLaunchKernelGGL(k_og_fwd, pgrid, dim3(kThreads), 0, sq, dsys, dst, parts);
       hipLaunchKernelGGL(k_og_alpha, dim3(n_sys), dim3(kThreads), 0, sq, dsys, dst, parts);
-      hipLaunchKernelGGL(k_og_update, vgrid, dim3(kThreads), 0, sq, dsys, dst);
-      OG_HIP(hipGetLastError());
-      if ((e = stencil_all(sq, 1, 0)) != WRI_OK) return e;
-      hipLaunchKernelGGL(k_og_scatter, ugrid, dim3(kThreads), 0, sq, dsys, dst, 0);
-      hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, sq, dsys, dst, 1, 0, parts);
+      hipLaunchKernelGGL(k_og_adj, pgrid, dim3(kThreads), 0, sq, dsys, dst, parts, 0);
       hipLaunchKernelGGL(k_og_beta, dim3(n_sys), dim3(kThreads), 0, sq, dsys, dst, parts);
-      hipLaunchKernelGGL(k_og_xpby, vgrid, dim3(kThreads), 0, sq, dsys, dst);
       OG_HIP(hipGetLastError());
     }
     return WRI_OK;
   };
-  // set-up: x = 0, r = b, s = S^H b
+  // set-up: x = 0, r_0 = b, s_0 = S^H b, gamma0
   hipLaunchKernelGGL(k_og_zero, vgrid, dim3(kThreads), 0, st, dsys);
-  OG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_og_init, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst);
-  OG_HIP(hipGetLastError());
-  if ((rc = stencil_all(st, 1, 1)) != WRI_OK) return rc;
-  hipLaunchKernelGGL(k_og_scatter, ugrid, dim3(kThreads), 0, st, dsys, dst, 1);
-  hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 1, 1, parts);
+  hipLaunchKernelGGL(k_og_adj, pgrid, dim3(kThreads), 0, st, dsys, dst, parts, 1);
   hipLaunchKernelGGL(k_og_start, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
-  hipLaunchKernelGGL(k_og_copy_ps, vgrid, dim3(kThreads), 0, st, dsys);
   OG_HIP(hipGetLastError());
   std::vector<OgState> hst(n_sys);
   auto read = [&]() -> int {
@@ -724,9 +740,9 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
   }
   release();
   // objective, source weights, gradient
-  hipLaunchKernelGGL(k_og_norm, pgrid, dim3(kThreads), 0, st, dsys, dst, 2, 1, parts);
+  hipLaunchKernelGGL(k_og_rnorm, pgrid, dim3(kThreads), 0, st, dsys, dst, parts);
+  if (mode == WRI_ESTIMATE) hipLaunchKernelGGL(k_og_ax, vgrid, dim3(kThreads), 0, st, dsys);
   OG_HIP(hipGetLastError());
-  if (mode == WRI_ESTIMATE && (rc = stencil_all(st, 2, 1)) != WRI_OK) return rc;
   hipLaunchKernelGGL(k_og_final, dim3(n_sys), dim3(kThreads), 0, st, dsys, dst, parts);
   OG_HIP(hipGetLastError());
   if (grad != nullptr)
