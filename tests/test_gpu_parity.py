@@ -643,3 +643,48 @@ def test_warm_start_zero_data_gives_zero():
         assert res[i]["status"] == "zero_rhs" and res[i]["iters"] == 0
         assert not torch.any(u[i] != 0)
         assert res[i]["alpha"] == 0
+
+
+def test_operator_adjoint_identity():
+    """<A p, y> = <p, A^H y> for the single-operator kernel (float64 sums of the
+    float32 outputs), on a grid of several tiles with a sponge."""
+    _say("adjoint identity")
+    g = wri_synth.Grid(70, 37, 19, h=12.5, nb=3, v_ref=1600.0)
+    rng = np.random.default_rng(31)
+    m = torch.tensor(rng.uniform(1 / 4000.0 ** 2, 1 / 1500.0 ** 2, g.n), dtype=torch.float32, device=DEV)
+    p = (rng.standard_normal(g.n) + 1j * rng.standard_normal(g.n)).astype(np.complex64)
+    y = (rng.standard_normal(g.n) + 1j * rng.standard_normal(g.n)).astype(np.complex64)
+    om = 2 * np.pi * 9.0
+    Ap = _np(wri.apply_helmholtz(g, m, om, torch.tensor(p, device=DEV)))
+    AHy = _np(wri.apply_helmholtz(g, m, om, torch.tensor(y, device=DEV), adjoint=True))
+    lhs = np.vdot(y.astype(np.complex128), Ap)
+    rhs = np.vdot(AHy, p.astype(np.complex128))
+    scale = np.linalg.norm(Ap) * np.linalg.norm(y)
+    assert abs(lhs - rhs) <= 1e-6 * scale, (lhs, rhs)
+
+
+def test_full_size_directional_derivative():
+    """128^3, 48 systems, rtol 1e-4: the central difference of the GPU
+    objective along a smooth model perturbation (a Gaussian bump of 5 % of m,
+    sigma 12 cells) matches g . dm from the gradient kernel to 2 % (measured
+    0.45 %).  With a 0.5 % bump the change of J, 1e-4 of J, is within 5 % of
+    the ~6e-6 scatter that the rtol-1e-4 solves leave in J; for the same
+    reason the Taylor remainder (second order, below 4e-6 here) is not
+    resolved at this size — it is checked on the oracle."""
+    _say("full size directional derivative")
+    p = wri_synth.make_config("differentiation", seed=0)
+    b = wri.Batch(p, device=DEV)
+    m0 = torch.tensor(np.asarray(p.m[0], dtype=np.float32).reshape(-1), device=DEV)
+    J0, g0, _ = wri.objective_grad(b)
+    g = p.grids[0]
+    z, y, x = np.meshgrid(*[np.arange(n) for n in g.shape], indexing="ij")
+    bump = np.exp(-(((x - 64.0) ** 2 + (y - 64.0) ** 2 + (z - 70.0) ** 2) / (2 * 12.0 ** 2)))
+    dm = torch.tensor((0.05 * bump * p.m[0]).reshape(-1).astype(np.float32), device=DEV)
+    gd = float((g0[0].double() * dm.double()).sum())
+    Js = {}
+    for t in (1.0, -1.0):
+        b.set_m([m0 + t * dm])
+        Js[t], _, _ = wri.objective_grad(b)
+    fd = (Js[1.0] - Js[-1.0]) / 2.0
+    _say(f"  J0 {J0:.8e}  g.dm {gd:.6e}  central difference {fd:.6e}")
+    assert abs(fd - gd) <= 2e-2 * abs(gd)
