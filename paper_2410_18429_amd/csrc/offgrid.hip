@@ -52,7 +52,7 @@ struct OgSys {
   const int* uptr; const int* ucell; const int* uq; const double* uw;
   const float* m;
   int n, ns, nr, nu;
-  int est, max_iter, nx, ny, nz, nb;
+  int est, max_iter, nx, ny, nz, nb, zc, pad2_;
   double c, lam, rtol2, omega, omega2, h2inv, sp_scale, inv_nb;
   double2 alpha;  // KNOWN-mode weight
 };
@@ -132,8 +132,13 @@ __global__ void __launch_bounds__(kThreads) k_og_init(const OgSys* __restrict__ 
   }
 }
 
+// Work items of the stencil passes: an (x, y) column and a chunk of S.zc planes
+// marched in z, the z-neighbours carried in registers (S.zc <= kZc, smaller on
+// small grids so that every thread of the kParts blocks has an item).
+constexpr int kZc = 16;
+
 // Forward pass of iteration k: p_k = s_k + beta p_{k-1} (computed at the cell
-// and its six neighbours), t = A p_k, per-block partials of ||t||^2 (the
+// and its neighbours), t = A p_k, per-block partials of ||t||^2 (the
 // source-column term is added by k_og_alpha).  grid (kParts, nsys).
 __global__ void __launch_bounds__(kThreads) k_og_fwd(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
                                                      double* __restrict__ parts) {
@@ -148,21 +153,30 @@ __global__ void __launch_bounds__(kThreads) k_og_fwd(const OgSys* __restrict__ s
     float2* __restrict__ pn = S.p[k & 1];
     const double beta = T.beta;
     const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny;
+    const int zcn = S.zc, items = plane * ((nz + zcn - 1) / zcn);
     const float2 zero = make_float2(0.f, 0.f);
-    for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += kParts * kThreads) {
-      const int z = c / plane, rem = c - z * plane, y = rem / nx, x = rem - y * nx;
-      const float2 pc = axpyd(sv[c], beta, po[c]);
-      const float2 xm = x > 0 ? axpyd(sv[c - 1], beta, po[c - 1]) : zero;
-      const float2 xp = x < nx - 1 ? axpyd(sv[c + 1], beta, po[c + 1]) : zero;
-      const float2 ym = y > 0 ? axpyd(sv[c - nx], beta, po[c - nx]) : zero;
-      const float2 yp = y < ny - 1 ? axpyd(sv[c + nx], beta, po[c + nx]) : zero;
-      const float2 zm = z > 0 ? axpyd(sv[c - plane], beta, po[c - plane]) : zero;
-      const float2 zp = z < nz - 1 ? axpyd(sv[c + plane], beta, po[c + plane]) : zero;
-      pn[c] = pc;
-      const float2 tv = round2(helm(pc, xm, xp, ym, yp, zm, zp, S.h2inv, S.omega2 * (double)S.m[c],
-                                    -(S.omega * sponge_at(S, x, y, z))));
-      S.t[c] = tv;
-      acc += nrm(tv);
+    auto P = [&](int c) { return axpyd(sv[c], beta, po[c]); };
+    for (int w = blockIdx.x * kThreads + threadIdx.x; w < items; w += kParts * kThreads) {
+      const int col = w % plane, zc = w / plane, y = col / nx, x = col - y * nx;
+      const int z0 = zc * zcn, z1 = min(z0 + zcn, nz);
+      const double sxy = sponge_axis_d(x, nx, S.nb, S.inv_nb) + sponge_axis_d(y, ny, S.nb, S.inv_nb);
+      float2 vm = z0 > 0 ? P((z0 - 1) * plane + col) : zero;
+      float2 vc = P(z0 * plane + col);
+      for (int z = z0; z < z1; ++z) {
+        const int c = z * plane + col;
+        const float2 vp = z + 1 < nz ? P(c + plane) : zero;
+        const float2 xm = x > 0 ? P(c - 1) : zero;
+        const float2 xp = x < nx - 1 ? P(c + 1) : zero;
+        const float2 ym = y > 0 ? P(c - nx) : zero;
+        const float2 yp = y < ny - 1 ? P(c + nx) : zero;
+        pn[c] = vc;
+        const double b = S.sp_scale * (sxy + sponge_axis_d(z, nz, S.nb, S.inv_nb));
+        const float2 tv = round2(helm(vc, xm, xp, ym, yp, vm, vp, S.h2inv, S.omega2 * (double)S.m[c], -(S.omega * b)));
+        S.t[c] = tv;
+        acc += nrm(tv);
+        vm = vc;
+        vc = vp;
+      }
     }
   }
   acc = bsum(acc, red);
@@ -216,7 +230,7 @@ __global__ void __launch_bounds__(kThreads) k_og_alpha(const OgSys* __restrict__
   }
 }
 
-// Adjoint pass: r_{k+1} = r_k - a t (at the cell and its six neighbours),
+// Adjoint pass: r_{k+1} = r_k - a t (at the cell and its neighbours),
 // s = A^H r_{k+1}, x += a p_k, per-block partials of ||s||^2 (the receiver
 // rows are added by k_og_beta).  setup = 1: the pass on r_0 with no update
 // (s_0 = A^H r_0, copied r_0 into r_1).  grid (kParts, nsys).
@@ -234,23 +248,31 @@ __global__ void __launch_bounds__(kThreads) k_og_adj(const OgSys* __restrict__ s
     const float2* __restrict__ tv = S.t;
     const float2* __restrict__ pk = S.p[k & 1];
     const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny;
+    const int zcn = S.zc, items = plane * ((nz + zcn - 1) / zcn);
     const float2 zero = make_float2(0.f, 0.f);
-    auto rnew = [&](int c) { return setup ? ro[c] : axpyd(ro[c], -a, tv[c]); };
-    for (int c = blockIdx.x * kThreads + threadIdx.x; c < S.n; c += kParts * kThreads) {
-      const int z = c / plane, rem = c - z * plane, y = rem / nx, x = rem - y * nx;
-      const float2 rc = rnew(c);
-      const float2 xm = x > 0 ? rnew(c - 1) : zero;
-      const float2 xp = x < nx - 1 ? rnew(c + 1) : zero;
-      const float2 ym = y > 0 ? rnew(c - nx) : zero;
-      const float2 yp = y < ny - 1 ? rnew(c + nx) : zero;
-      const float2 zm = z > 0 ? rnew(c - plane) : zero;
-      const float2 zp = z < nz - 1 ? rnew(c + plane) : zero;
-      rn[c] = rc;
-      const float2 sv = round2(helm(rc, xm, xp, ym, yp, zm, zp, S.h2inv, S.omega2 * (double)S.m[c],
-                                    S.omega * sponge_at(S, x, y, z)));
-      S.s[c] = sv;
-      acc += nrm(sv);
-      if (!setup) S.x[c] = axpyd(S.x[c], a, pk[c]);
+    auto R = [&](int c) { return setup ? ro[c] : axpyd(ro[c], -a, tv[c]); };
+    for (int w = blockIdx.x * kThreads + threadIdx.x; w < items; w += kParts * kThreads) {
+      const int col = w % plane, zc = w / plane, y = col / nx, x = col - y * nx;
+      const int z0 = zc * zcn, z1 = min(z0 + zcn, nz);
+      const double sxy = sponge_axis_d(x, nx, S.nb, S.inv_nb) + sponge_axis_d(y, ny, S.nb, S.inv_nb);
+      float2 vm = z0 > 0 ? R((z0 - 1) * plane + col) : zero;
+      float2 vc = R(z0 * plane + col);
+      for (int z = z0; z < z1; ++z) {
+        const int c = z * plane + col;
+        const float2 vp = z + 1 < nz ? R(c + plane) : zero;
+        const float2 xm = x > 0 ? R(c - 1) : zero;
+        const float2 xp = x < nx - 1 ? R(c + 1) : zero;
+        const float2 ym = y > 0 ? R(c - nx) : zero;
+        const float2 yp = y < ny - 1 ? R(c + nx) : zero;
+        rn[c] = vc;
+        const double b = S.sp_scale * (sxy + sponge_axis_d(z, nz, S.nb, S.inv_nb));
+        const float2 sv = round2(helm(vc, xm, xp, ym, yp, vm, vp, S.h2inv, S.omega2 * (double)S.m[c], S.omega * b));
+        S.s[c] = sv;
+        acc += nrm(sv);
+        if (!setup) S.x[c] = axpyd(S.x[c], a, pk[c]);
+        vm = vc;
+        vc = vp;
+      }
     }
   }
   acc = bsum(acc, red);
@@ -633,6 +655,7 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
     S.alpha = make_double2(s.alpha.re, s.alpha.im);
     S.m = m[s.grid];
     S.nx = g.nx; S.ny = g.ny; S.nz = g.nz; S.nb = g.nb;
+    S.zc = (int)std::max<int64_t>(1, std::min<int64_t>(kZc, n / ((int64_t)kParts * kThreads)));
     S.h2inv = 1.0 / (g.h * g.h);
     if (g.nb > 0) {
       const double d0 = 3.0 * g.v_ref * std::log(1000.0) / (2.0 * g.nb * g.h);
