@@ -132,10 +132,46 @@ __global__ void __launch_bounds__(kThreads) k_og_init(const OgSys* __restrict__ 
   }
 }
 
-// Work items of the stencil passes: an (x, y) column and a chunk of S.zc planes
-// marched in z, the z-neighbours carried in registers (S.zc <= kZc, smaller on
-// small grids so that every thread of the kParts blocks has an item).
+// Work items of the stencil passes: a 64 x 4 tile of (x, y) columns (one
+// thread each) and a chunk of S.zc planes marched in z.  Each plane of the
+// recomputed vector (p_k or r_{k+1}) is staged with a one-cell halo in LDS for
+// the x/y neighbours; the z-neighbours stay in registers.  Every block runs
+// the same number of items and planes (the barriers are uniform); threads
+// outside the grid hold zeros.
 constexpr int kZc = 16;
+constexpr int kTy = kThreads / 64;               // tile rows
+constexpr int kHalo = 2 * (64 + 2) + 2 * kTy;    // halo cells of one tile plane
+
+struct TileWork {
+  int x, y, z0, z1, col;
+  bool in;
+};
+
+__device__ __forceinline__ int tile_items(const OgSys& S) {
+  return ((S.nx + 63) / 64) * ((S.ny + kTy - 1) / kTy) * ((S.nz + S.zc - 1) / S.zc);
+}
+
+__device__ __forceinline__ TileWork tile_work(const OgSys& S, int w) {
+  const int tx_n = (S.nx + 63) / 64, ty_n = (S.ny + kTy - 1) / kTy;
+  const int t = w % (tx_n * ty_n), zc = w / (tx_n * ty_n);
+  TileWork W;
+  W.x = (t % tx_n) * 64 + (threadIdx.x & 63);
+  W.y = (t / tx_n) * kTy + (threadIdx.x >> 6);
+  W.z0 = zc * S.zc;
+  W.z1 = min(W.z0 + S.zc, S.nz);
+  W.in = W.x < S.nx && W.y < S.ny;
+  W.col = W.y * S.nx + W.x;
+  return W;
+}
+
+// halo cell h of the tile containing (x0, y0) (its corner cell): LDS slot and grid cell
+__device__ __forceinline__ void halo_cell(int h, int x0, int y0, int* hx, int* hy, int* gx, int* gy) {
+  if (h < 66) { *hy = 0; *hx = h; }
+  else if (h < 132) { *hy = kTy + 1; *hx = h - 66; }
+  else { const int q = h - 132; *hy = 1 + (q >> 1); *hx = (q & 1) ? 65 : 0; }
+  *gx = x0 + *hx - 1;
+  *gy = y0 + *hy - 1;
+}
 
 // Forward pass of iteration k: p_k = s_k + beta p_{k-1} (computed at the cell
 // and its neighbours), t = A p_k, per-block partials of ||t||^2 (the
@@ -143,6 +179,7 @@ constexpr int kZc = 16;
 __global__ void __launch_bounds__(kThreads) k_og_fwd(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
                                                      double* __restrict__ parts) {
   __shared__ double red[kThreads / 64];
+  __shared__ float2 pl[kTy + 2][66];
   const OgSys& S = sy[blockIdx.y];
   const OgState& T = stv[blockIdx.y];
   double acc = 0.0;
@@ -153,27 +190,33 @@ __global__ void __launch_bounds__(kThreads) k_og_fwd(const OgSys* __restrict__ s
     float2* __restrict__ pn = S.p[k & 1];
     const double beta = T.beta;
     const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny;
-    const int zcn = S.zc, items = plane * ((nz + zcn - 1) / zcn);
     const float2 zero = make_float2(0.f, 0.f);
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     auto P = [&](int c) { return axpyd(sv[c], beta, po[c]); };
-    for (int w = blockIdx.x * kThreads + threadIdx.x; w < items; w += kParts * kThreads) {
-      const int col = w % plane, zc = w / plane, y = col / nx, x = col - y * nx;
-      const int z0 = zc * zcn, z1 = min(z0 + zcn, nz);
-      const double sxy = sponge_axis_d(x, nx, S.nb, S.inv_nb) + sponge_axis_d(y, ny, S.nb, S.inv_nb);
-      float2 vm = z0 > 0 ? P((z0 - 1) * plane + col) : zero;
-      float2 vc = P(z0 * plane + col);
-      for (int z = z0; z < z1; ++z) {
-        const int c = z * plane + col;
-        const float2 vp = z + 1 < nz ? P(c + plane) : zero;
-        const float2 xm = x > 0 ? P(c - 1) : zero;
-        const float2 xp = x < nx - 1 ? P(c + 1) : zero;
-        const float2 ym = y > 0 ? P(c - nx) : zero;
-        const float2 yp = y < ny - 1 ? P(c + nx) : zero;
-        pn[c] = vc;
-        const double b = S.sp_scale * (sxy + sponge_axis_d(z, nz, S.nb, S.inv_nb));
-        const float2 tv = round2(helm(vc, xm, xp, ym, yp, vm, vp, S.h2inv, S.omega2 * (double)S.m[c], -(S.omega * b)));
-        S.t[c] = tv;
-        acc += nrm(tv);
+    const int items = tile_items(S);
+    for (int w = blockIdx.x; w < items; w += kParts) {
+      const TileWork W = tile_work(S, w);
+      int hx = 0, hy = 0, gx = -1, gy = -1;
+      if ((int)threadIdx.x < kHalo) halo_cell(threadIdx.x, W.x - lx, W.y - ly, &hx, &hy, &gx, &gy);
+      const bool hin = (int)threadIdx.x < kHalo && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      const double sxy = W.in ? sponge_axis_d(W.x, nx, S.nb, S.inv_nb) + sponge_axis_d(W.y, ny, S.nb, S.inv_nb) : 0.0;
+      float2 vm = (W.in && W.z0 > 0) ? P((W.z0 - 1) * plane + W.col) : zero;
+      float2 vc = W.in ? P(W.z0 * plane + W.col) : zero;
+      for (int z = W.z0; z < W.z1; ++z) {
+        pl[ly + 1][lx + 1] = vc;
+        if ((int)threadIdx.x < kHalo) pl[hy][hx] = hin ? P(z * plane + gy * nx + gx) : zero;
+        __syncthreads();
+        const int c = z * plane + W.col;
+        const float2 vp = (W.in && z + 1 < nz) ? P(c + plane) : zero;
+        if (W.in) {
+          pn[c] = vc;
+          const double b = S.sp_scale * (sxy + sponge_axis_d(z, nz, S.nb, S.inv_nb));
+          const float2 tv = round2(helm(vc, pl[ly + 1][lx], pl[ly + 1][lx + 2], pl[ly][lx + 1], pl[ly + 2][lx + 1], vm,
+                                        vp, S.h2inv, S.omega2 * (double)S.m[c], -(S.omega * b)));
+          S.t[c] = tv;
+          acc += nrm(tv);
+        }
+        __syncthreads();
         vm = vc;
         vc = vp;
       }
@@ -233,10 +276,12 @@ __global__ void __launch_bounds__(kThreads) k_og_alpha(const OgSys* __restrict__
 // Adjoint pass: r_{k+1} = r_k - a t (at the cell and its neighbours),
 // s = A^H r_{k+1}, x += a p_k, per-block partials of ||s||^2 (the receiver
 // rows are added by k_og_beta).  setup = 1: the pass on r_0 with no update
-// (s_0 = A^H r_0, copied r_0 into r_1).  grid (kParts, nsys).
+// (s_0 = A^H r_0, copied r_0 into r_1).  Same tiles as k_og_fwd.
+// grid (kParts, nsys).
 __global__ void __launch_bounds__(kThreads) k_og_adj(const OgSys* __restrict__ sy, const OgState* __restrict__ stv,
                                                      double* __restrict__ parts, int setup) {
   __shared__ double red[kThreads / 64];
+  __shared__ float2 pl[kTy + 2][66];
   const OgSys& S = sy[blockIdx.y];
   const OgState& T = stv[blockIdx.y];
   double acc = 0.0;
@@ -248,28 +293,34 @@ __global__ void __launch_bounds__(kThreads) k_og_adj(const OgSys* __restrict__ s
     const float2* __restrict__ tv = S.t;
     const float2* __restrict__ pk = S.p[k & 1];
     const int nx = S.nx, ny = S.ny, nz = S.nz, plane = nx * ny;
-    const int zcn = S.zc, items = plane * ((nz + zcn - 1) / zcn);
     const float2 zero = make_float2(0.f, 0.f);
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     auto R = [&](int c) { return setup ? ro[c] : axpyd(ro[c], -a, tv[c]); };
-    for (int w = blockIdx.x * kThreads + threadIdx.x; w < items; w += kParts * kThreads) {
-      const int col = w % plane, zc = w / plane, y = col / nx, x = col - y * nx;
-      const int z0 = zc * zcn, z1 = min(z0 + zcn, nz);
-      const double sxy = sponge_axis_d(x, nx, S.nb, S.inv_nb) + sponge_axis_d(y, ny, S.nb, S.inv_nb);
-      float2 vm = z0 > 0 ? R((z0 - 1) * plane + col) : zero;
-      float2 vc = R(z0 * plane + col);
-      for (int z = z0; z < z1; ++z) {
-        const int c = z * plane + col;
-        const float2 vp = z + 1 < nz ? R(c + plane) : zero;
-        const float2 xm = x > 0 ? R(c - 1) : zero;
-        const float2 xp = x < nx - 1 ? R(c + 1) : zero;
-        const float2 ym = y > 0 ? R(c - nx) : zero;
-        const float2 yp = y < ny - 1 ? R(c + nx) : zero;
-        rn[c] = vc;
-        const double b = S.sp_scale * (sxy + sponge_axis_d(z, nz, S.nb, S.inv_nb));
-        const float2 sv = round2(helm(vc, xm, xp, ym, yp, vm, vp, S.h2inv, S.omega2 * (double)S.m[c], S.omega * b));
-        S.s[c] = sv;
-        acc += nrm(sv);
-        if (!setup) S.x[c] = axpyd(S.x[c], a, pk[c]);
+    const int items = tile_items(S);
+    for (int w = blockIdx.x; w < items; w += kParts) {
+      const TileWork W = tile_work(S, w);
+      int hx = 0, hy = 0, gx = -1, gy = -1;
+      if ((int)threadIdx.x < kHalo) halo_cell(threadIdx.x, W.x - lx, W.y - ly, &hx, &hy, &gx, &gy);
+      const bool hin = (int)threadIdx.x < kHalo && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      const double sxy = W.in ? sponge_axis_d(W.x, nx, S.nb, S.inv_nb) + sponge_axis_d(W.y, ny, S.nb, S.inv_nb) : 0.0;
+      float2 vm = (W.in && W.z0 > 0) ? R((W.z0 - 1) * plane + W.col) : zero;
+      float2 vc = W.in ? R(W.z0 * plane + W.col) : zero;
+      for (int z = W.z0; z < W.z1; ++z) {
+        pl[ly + 1][lx + 1] = vc;
+        if ((int)threadIdx.x < kHalo) pl[hy][hx] = hin ? R(z * plane + gy * nx + gx) : zero;
+        __syncthreads();
+        const int c = z * plane + W.col;
+        const float2 vp = (W.in && z + 1 < nz) ? R(c + plane) : zero;
+        if (W.in) {
+          rn[c] = vc;
+          const double b = S.sp_scale * (sxy + sponge_axis_d(z, nz, S.nb, S.inv_nb));
+          const float2 sv = round2(helm(vc, pl[ly + 1][lx], pl[ly + 1][lx + 2], pl[ly][lx + 1], pl[ly + 2][lx + 1], vm,
+                                        vp, S.h2inv, S.omega2 * (double)S.m[c], S.omega * b));
+          S.s[c] = sv;
+          acc += nrm(sv);
+          if (!setup) S.x[c] = axpyd(S.x[c], a, pk[c]);
+        }
+        __syncthreads();
         vm = vc;
         vc = vp;
       }
@@ -655,7 +706,7 @@ int og_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
     S.alpha = make_double2(s.alpha.re, s.alpha.im);
     S.m = m[s.grid];
     S.nx = g.nx; S.ny = g.ny; S.nz = g.nz; S.nb = g.nb;
-    S.zc = (int)std::max<int64_t>(1, std::min<int64_t>(kZc, n / ((int64_t)kParts * kThreads)));
+    S.zc = (int)std::max<int64_t>(1, std::min<int64_t>(kZc, n / ((int64_t)kParts * kThreads)));  // >= kParts items
     S.h2inv = 1.0 / (g.h * g.h);
     if (g.nb > 0) {
       const double d0 = 3.0 * g.v_ref * std::log(1000.0) / (2.0 * g.nb * g.h);
