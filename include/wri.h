@@ -69,8 +69,8 @@ extern "C" {
 typedef struct { float re, im; } wri_c32;
 typedef struct { double re, im; } wri_c64;
 
-/* One grid. nx*ny*nz < 2^31 cells and nx*ny <= 3834792 cells per x-y plane
- * (70 planes of complex64 addressable with 32-bit offsets); h > 0 [m]; nb >= 0 sponge cells;
+/* One grid. nx*ny*nz < 2^31 cells and nx*ny <= 3728270 cells per x-y plane
+ * (72 planes of complex64 addressable with 32-bit offsets); h > 0 [m]; nb >= 0 sponge cells;
  * v_ref > 0 [m/s] (sponge reference velocity; ignored when nb == 0). */
 typedef struct {
   int32_t nx, ny, nz;

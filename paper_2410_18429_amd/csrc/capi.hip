@@ -29,10 +29,12 @@ thread_local std::string g_last_error;
 //   forward k: reads s, p_{k-1}, m; writes p_k, t                       36 B
 //              + at even k >= 2 reads x, p_{k-2} and writes x           24 B
 //   adjoint k: reads r_k, t, m; writes r_{k+1}, s                       36 B
+// With t recomputed in the adjoint pass (tile pf >= 2) the forward pass does
+// not write t (28 B) and the adjoint pass reads p_k in its place (36 B).
 // Halo re-reads and the receiver rows are not counted.
-constexpr int kFwdBytesPerCell = 36, kFwdXBytesPerCell = 24, kAdjBytesPerCell = 36;
-inline int fwd_bytes_per_cell(int64_t k) {
-  return kFwdBytesPerCell + ((k >= 2 && (k & 1) == 0) ? kFwdXBytesPerCell : 0);
+constexpr int kFwdBytesPerCell = 36, kFwdXBytesPerCell = 24, kAdjBytesPerCell = 36, kTBytesPerCell = 8;
+inline int fwd_bytes_per_cell(int64_t k, int pf) {
+  return kFwdBytesPerCell - (pf >= 2 ? kTBytesPerCell : 0) + ((k >= 2 && (k & 1) == 0) ? kFwdXBytesPerCell : 0);
 }
 
 struct KernelTimes {
@@ -69,6 +71,8 @@ const TileCfg kCands[] = {
     {4, 1, 32, 1, 1}, {4, 1, 64, 1, 1}, {4, 4, 32, 1, 1}, {4, 2, 32, 0, 1}, {8, 1, 16, 0, 1},
     {8, 2, 16, 0, 1}, {4, 2, 16, 0, 0}, {8, 1, 16, 0, 0}, {2, 8, 32, 0, 0}, {4, 4, 16, 0, 1},
     {8, 1, 32, 1, 2}, {8, 1, 32, 1, 4}, {8, 1, 32, 1, 8}, {4, 2, 32, 1, 2},
+    {8, 1, 32, 2, 4}, {8, 2, 32, 2, 4}, {4, 4, 32, 2, 4}, {4, 2, 32, 2, 4}, {8, 1, 32, 2, 0},
+    {8, 1, 32, 3, 4}, {4, 2, 32, 3, 4}, {4, 2, 64, 2, 4}, {4, 2, 16, 2, 4}, {8, 1, 64, 3, 4},
 };
 constexpr int kNumCands = sizeof(kCands) / sizeof(kCands[0]);
 
@@ -99,7 +103,7 @@ int64_t cells(const wri_grid& g) { return (int64_t)g.nx * g.ny * g.nz; }
 // validation (host only)
 // ---------------------------------------------------------------------------
 
-constexpr int64_t kMaxPlaneSpan = 70;  // planes one slab's buffer resources may span (z-slab <= 64, + halo)
+constexpr int64_t kMaxPlaneSpan = 72;  // planes a slab's buffer offsets may span (z-slab <= 64, halo, prefetch)
 
 int validate(const wri_grid* grids, int32_t n_grids, const wri_system* sys, int32_t n_sys, int32_t mode,
              int32_t max_iter) {
@@ -112,7 +116,7 @@ int validate(const wri_grid* grids, int32_t n_grids, const wri_system* sys, int3
     const wri_grid& g = grids[i];
     if (g.nx < 1 || g.ny < 1 || g.nz < 1) return fail(WRI_EINVAL, "grid %d: non-positive size", i);
     if (cells(g) >= (int64_t(1) << 31)) return fail(WRI_EINVAL, "grid %d: more than 2^31-1 cells", i);
-    // the fused kernels address up to 70 planes of complex64 with 32-bit byte offsets
+    // the fused kernels address up to 72 planes of complex64 with 32-bit byte offsets
     if ((int64_t)g.nx * g.ny * kMaxPlaneSpan * 8 >= (int64_t(1) << 31))
       return fail(WRI_EINVAL, "grid %d: more than %lld cells in one x-y plane", i,
                   (long long)(((int64_t(1) << 31) - 1) / (kMaxPlaneSpan * 8)));
@@ -706,13 +710,14 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
         wri_timing& T = g_times.t;
         // algorithmic bytes of each launch of the chunk: a system takes part in
         // launch k with full work while k < its final iteration count
+        const int pf = cur_cfg(C).pf;
         for (int i = 0; i < chunk; ++i) {
           const int64_t k = kstart + i;
           double fb = 0.0, ab = 0.0;
           for (int p = 0; p < C.n_sys; ++p) {
             if (hs[p].status != kActive && hs[p].iters <= k) continue;
             const double n = (double)cells(C.grids[C.sys[L.order[p]].grid]);
-            fb += n * (double)fwd_bytes_per_cell(k);
+            fb += n * (double)fwd_bytes_per_cell(k, pf);
             ab += n * (double)kAdjBytesPerCell;
           }
           T.fwd_bytes += fb;

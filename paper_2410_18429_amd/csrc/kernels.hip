@@ -818,7 +818,9 @@ struct RecMask {
   __device__ int take(const SysDev& S, int j) { return ld2i(gptr(S.entries), cur[j]++).y; }
 };
 
-template <int W, int RY, int XS>
+// TR = 1: t is not stored (the adjoint pass k_adj_rc recomputes it from p_k);
+// the receiver rows t2 and the partials of ||t||^2 are the same.
+template <int W, int RY, int XS, int TR>
 __global__ void __launch_bounds__(64 * W)
 k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_s,
          double* __restrict__ part_d, const GroupDesc* __restrict__ gd, int ngroups) {
@@ -1054,7 +1056,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       const float2 tv = round2(td);
       const bool live = C.in[j] && zin;
       const unsigned o8 = own_b(z, j, 8) | zbit;
-      bst2(Rt, o8, tv);
+      if constexpr (TR == 0) bst2(Rt, o8, tv);
       bst2(Rpn, o8, pc[j]);
       acc += live ? norm2d(tv) : 0.0;
       if (rc.at(j, z - C.z0)) {  // receiver row of S p: lambda p at the receiver cell
@@ -1321,13 +1323,397 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 }
 
 // ---------------------------------------------------------------------------
+// fused adjoint kernel with t recomputed: the forward pass stores no t
+// ---------------------------------------------------------------------------
+// r_{k+1} = r_k - a_k t is needed on the tile and on a one-cell ring around it
+// (the stencil of s = A^H r_{k+1}), so t = S p_k is evaluated there, which
+// takes p_k on a two-cell ring.  t comes from the same stencil routine, with
+// the same operands in the same order, as in the forward pass, so it has the
+// bits the forward pass would have stored, and the iterates are identical to
+// those of k_adj_pf.  Bytes per (system, cell): read r_k, p_k, m (8+8+4), write
+// r_{k+1}, s (8+8) = 36 B; the forward pass drops its 8 B store of t.
+//
+// March over the slab, step for plane z: s of plane z from the r_{k+1} planes
+// z-1..z+1 (LDS ring of three, z-neighbours of the own rows in registers);
+// then t and r_{k+1} of plane z+2 on tile + ring 1 from the p_k plane z+2 (LDS,
+// two rings) and the p_k planes z+1, z+3 (registers); then p_k of plane z+3 is
+// committed to the other LDS buffer and the loads of plane z+2+NS (r_k, m) and
+// z+3+NS (p_k) are issued into raw register set NS: with NS = 2 the sets
+// alternate between even and odd steps, so a load has two steps to arrive (at
+// the cost of registers, i.e. of resident waves).  A loaded register is
+// consumed where it lands and never copied while in flight.
+// A register copy the compiler cannot coalesce with its source: a loaded
+// register that is kept for later planes is copied out once it has been used,
+// so the load's own register dies there and the next load of the march can
+// land in it (a coalesced copy keeps it alive, and the next load then goes to
+// a fresh register that has to be copied, with a wait, at the loop back-edge).
+__device__ __forceinline__ float keep1(float v) {
+  float r;
+  asm("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
+  return r;
+}
+__device__ __forceinline__ float2 keep2(float2 v) { return make_float2(keep1(v.x), keep1(v.y)); }
+
+template <int W, int RY, int NS>
+__global__ void __launch_bounds__(64 * W)
+k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_d,
+         double* __restrict__ part_s, const GroupDesc* __restrict__ gd, int ngroups, int setup_only) {
+  using Ctx = TileCtx<W, RY>;
+  constexpr int NT = 64 * W;
+  constexpr int LX = Ctx::LX, LY = Ctx::LY;  // r_{k+1} plane: tile and ring 1
+  constexpr int PX = LX + 2, PY = LY + 2;    // p_k plane: tile and rings 1, 2
+  constexpr int NH = Ctx::NH;                // ring-1 cells
+  constexpr int NH2 = 2 * PX + 2 * LY;       // ring-2 cells
+  constexpr int HS = (NH + NT - 1) / NT;
+  constexpr int HS2 = (NH2 + NT - 1) / NT;
+  __shared__ float2 pl[3][LY][LX];
+  __shared__ float2 pp[2][PY][PX];
+  __shared__ double red[W + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x, gd[0].xchunk);
+  int g = 0;
+  while (g + 1 < ngroups && logical >= gd[g + 1].block0) ++g;
+  const int ntiles = gd[g].ntiles, tiles_x = gd[g].tiles_x, tiles_y = gd[g].tiles_y, tz = gd[g].tz;
+  const int local = logical - gd[g].block0;
+  int rl, tile;
+  block_map(gd[g], local, &rl, &tile);
+  const int rhs = gd[g].rhs0 + rl;
+  const SysDev& S = sysv[rhs];
+  SysState* T = stv + rhs;
+  if (T->status != kActive) return;
+  const int k = T->iterB;
+  const bool setup = k < 0;
+  if (setup_only && !setup) return;
+
+  double a = 0.0;
+  double2 pa = make_double2(0.0, 0.0);
+  if (!setup) {
+    const double gk = T->gamma[k & 1];
+    const double g0 = T->gamma0;
+    const double gmin = (k == 0) ? gk : T->gmin[(k - 1) & 1];
+    const bool brk = T->brk != 0;
+    const bool stop = brk || (g0 == 0.0) || (gk <= S.rtol2 * g0) || (k >= S.max_iter) || (gk > kDivergeRatio * gmin);
+    if (stop) {
+      if (tile == 0 && tid == 0) {
+        T->status = brk ? kBreakdown
+                  : (g0 == 0.0) ? kZeroRhs
+                  : (gk <= S.rtol2 * g0) ? kConverged
+                  : (gk > kDivergeRatio * gmin) ? kDiverged : kMaxIter;
+        T->iters = k;
+      }
+      return;
+    }
+    const double dk = block_sum_slots<W>(part_d + S.slot_base, ntiles, red);
+    if (!(dk > 0.0) || !(dk <= DBL_MAX) || !(gk <= DBL_MAX)) {
+      if (tile == 0 && tid == 0) T->brk = 1;
+      return;
+    }
+    a = gk / dk;
+    if (tile == 0 && tid == 0) T->a[k & 1] = a;
+    if (S.mode == 1) pa = T->pa;  // p_alpha of this k (the forward pass wrote it)
+  }
+
+  Ctx C;
+  C.setup(S, tile, lane, w, tiles_x, tiles_y, tz);
+  const int plane = C.plane;
+  const double af = a;
+  const double w2 = S.omega_d * S.omega_d;
+  int coff[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
+
+  const int sxy = S.src % plane, sz = S.src / plane;
+  const int sx = sxy % S.nx, sy = sxy / S.nx;
+  int srcj = -1;  // own row holding the source column (mode 1)
+  if (S.mode == 1 && sx == C.gx) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+      if (C.gy[j] == sy) srcj = j;
+  }
+  const bool src_in_slab = sz >= C.z0 && sz < C.z1;
+
+  RecMask<RY> rc;
+  rc.setup(S, C.gx, C.gy, C.in, C.z0, C.z1);
+
+  double sxy2[RY];
+  const double sx2 = sponge_axis_d(C.gx, S.nx, S.nb, S.inv_nb_d);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) sxy2[j] = sx2 + sponge_axis_d(C.gy[j], S.ny, S.nb, S.inv_nb_d);
+
+  // r_k and m over planes [zlo, zhi) (t and r_{k+1} are needed one plane
+  // beyond the slab), p_k over [plo, phi) (two planes beyond)
+  const int zlo = max(C.z0 - 1, 0), zhi = min(C.z1 + 1, S.nz);
+  const int plo = max(C.z0 - 2, 0), phi = min(C.z1 + 2, S.nz);
+  const int64_t pl64 = plane;
+  const BufRes Rro = mkbuf(S.r[setup ? 1 : (k & 1)], zlo * pl64, (zhi - zlo) * pl64, 8);
+  const BufRes Rp = mkbuf(S.p[(k + 1) & 1], plo * pl64, (phi - plo) * pl64, 8);
+  const BufRes Rm = mkbuf(S.m, zlo * pl64, (zhi - zlo) * pl64, 4);
+  const BufRes Rrn = mkbuf(S.r[setup ? 0 : ((k + 1) & 1)], C.z0 * pl64, (C.z1 - C.z0) * pl64, 8);
+  const BufRes Rso = mkbuf(S.s, C.z0 * pl64, (C.z1 - C.z0) * pl64, 8);
+  GLOBAL float2* __restrict__ r2v = gptr(S.r2);
+  const GLOBAL float2* __restrict__ t2v = gptr((const float2*)S.t2);
+
+  // ring 1: LDS coordinates in the r_{k+1} plane (the p_k plane has them +1),
+  // cell offset, inside-grid flag, sponge of its column, source column flag
+  int hx[HS], hy[HS], hoff[HS];
+  bool hin[HS], hsrc[HS];
+  double hsxy[HS];
+#pragma unroll
+  for (int q = 0; q < HS; ++q) {
+    const int h = tid + q * NT;
+    hx[q] = 0; hy[q] = 0; hoff[q] = 0; hin[q] = false; hsrc[q] = false; hsxy[q] = 0.0;
+    if (h < NH) {
+      Ctx::halo_xy(h, hx[q], hy[q]);
+      const int xx = C.x0 + hx[q] - 1, yy = C.y0 + hy[q] - 1;
+      hin[q] = xx >= 0 && xx < S.nx && yy >= 0 && yy < S.ny;
+      hoff[q] = yy * S.nx + xx;
+      hsrc[q] = S.mode == 1 && xx == sx && yy == sy;
+      hsxy[q] = sponge_axis_d(xx, S.nx, S.nb, S.inv_nb_d) + sponge_axis_d(yy, S.ny, S.nb, S.inv_nb_d);
+    }
+  }
+  // ring 2: LDS coordinates in the p_k plane and cell offset
+  int gx2[HS2], gy2[HS2], goff[HS2];
+  bool gin[HS2];
+#pragma unroll
+  for (int q = 0; q < HS2; ++q) {
+    const int h = tid + q * NT;
+    gx2[q] = 0; gy2[q] = 0; goff[q] = 0; gin[q] = false;
+    if (h < NH2) {
+      if (h < PX) { gx2[q] = h; gy2[q] = 0; }
+      else if (h < 2 * PX) { gx2[q] = h - PX; gy2[q] = PY - 1; }
+      else { const int h2 = h - 2 * PX; gy2[q] = 1 + (h2 >> 1); gx2[q] = (h2 & 1) ? (PX - 1) : 0; }
+      const int xx = C.x0 + gx2[q] - 2, yy = C.y0 + gy2[q] - 2;
+      gin[q] = xx >= 0 && xx < S.nx && yy >= 0 && yy < S.ny;
+      goff[q] = yy * S.nx + xx;
+    }
+  }
+  // Byte offsets (see k_adj_pf): out-of-grid cells carry the out-of-range bit;
+  // planes outside a resource's range are out of range by themselves.  The
+  // set-up pass (s_0 = S^H b) reads no p.
+  const unsigned pbit = setup ? kOOB : 0u;
+  unsigned obit[RY], hbit[HS], gbit[HS2];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) obit[j] = C.in[j] ? 0u : kOOB;
+#pragma unroll
+  for (int q = 0; q < HS; ++q) hbit[q] = hin[q] ? 0u : kOOB;
+#pragma unroll
+  for (int q = 0; q < HS2; ++q) gbit[q] = gin[q] ? 0u : kOOB;
+  auto off_r = [&](int zz, int cell, unsigned bit, int elem) -> unsigned {
+    return (unsigned)(((zz - zlo) * plane + cell) * elem) | bit;
+  };
+  auto off_p = [&](int zz, int cell, unsigned bit) -> unsigned {
+    return (unsigned)(((zz - plo) * plane + cell) * 8) | bit | pbit;
+  };
+  auto own_b = [&](int zz, int j) -> unsigned {
+    return (unsigned)(((zz - C.z0) * plane + coff[j]) * 8) | obit[j];
+  };
+
+  // raw loads of one step, NS sets: p_k (own, ring 1, ring 2), r_k and m (own, ring 1)
+  float2 rp[NS][RY], hp[NS][HS], gp[NS][HS2], rr[NS][RY], hr[NS][HS];
+  float rmr[NS][RY], hmr[NS][HS];
+  auto issue = [&](const int st, int zr, int zp) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      rp[st][j] = bld2(Rp, off_p(zp, coff[j], obit[j]));
+      rr[st][j] = bld2(Rro, off_r(zr, coff[j], obit[j], 8));
+      rmr[st][j] = bld1(Rm, off_r(zr, coff[j], obit[j], 4));
+    }
+#pragma unroll
+    for (int q = 0; q < HS; ++q) {
+      hp[st][q] = bld2(Rp, off_p(zp, hoff[q], hbit[q]));
+      hr[st][q] = bld2(Rro, off_r(zr, hoff[q], hbit[q], 8));
+      hmr[st][q] = bld1(Rm, off_r(zr, hoff[q], hbit[q], 4));
+    }
+#pragma unroll
+    for (int q = 0; q < HS2; ++q) gp[st][q] = bld2(Rp, off_p(zp, goff[q], gbit[q]));
+  };
+  // p_k of planes zz-1, zz (own rows and ring 1); the raw load holds plane zz+1
+  float2 pzm[RY], pzc[RY], hpm[HS], hpc[HS];
+  // m of the own rows: planes z, z+1 (for s), then plane z+2 after tphase
+  float mq0[RY], mq1[RY], mq2[RY];
+  float2 rnew[RY];
+  // t and r_{k+1} of plane zz on tile + ring 1 from LDS p buffer bp; r_{k+1}
+  // into LDS buffer br (br < 0: own rows only) from raw set st; commit p_k of
+  // plane zz+1 to LDS buffer bp ^ 1 and move the p registers up one plane.
+  auto tphase = [&](const int st, int zz, int bp, int br) __attribute__((always_inline)) {
+    const bool zok = zz >= 0 && zz < S.nz;
+    const double sz2 = sponge_axis_d(zz, S.nz, S.nb, S.inv_nb_d);
+    const bool zsrc = zz == sz;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      const int ly = w * RY + j + 2;
+      const float2 xm = pp[bp][ly][lane + 1];
+      const float2 xp = pp[bp][ly][lane + 3];
+      const float2 ym = (j > 0) ? pzc[j > 0 ? j - 1 : 0] : pp[bp][ly - 1][lane + 2];
+      const float2 yp = (j < RY - 1) ? pzc[j < RY - 1 ? j + 1 : 0] : pp[bp][ly + 1][lane + 2];
+      const double b = S.sp_scale_d * (sxy2[j] + sz2);
+      double2 td = helm(pzc[j], xm, xp, ym, yp, pzm[j], rp[st][j], S.h2inv_d, w2 * (double)rmr[st][j],
+                         -(S.omega_d * b));
+      if (j == srcj && zsrc) {
+        td.x -= S.alpha_c * pa.x;
+        td.y -= S.alpha_c * pa.y;
+      }
+      const double ae = (zok && C.in[j]) ? af : 0.0;
+      rnew[j] = setup ? rr[st][j] : axpy2(rr[st][j], -ae, round2(td));
+      if (br >= 0) pl[br][ly - 1][lane + 1] = rnew[j];
+      mq2[j] = keep1(rmr[st][j]);
+    }
+#pragma unroll
+    for (int q = 0; q < HS; ++q) {
+      if (tid + q * NT < NH) {
+        const int cx = hx[q] + 1, cy = hy[q] + 1;
+        const float2 xm = pp[bp][cy][cx - 1];
+        const float2 xp = pp[bp][cy][cx + 1];
+        const float2 ym = pp[bp][cy - 1][cx];
+        const float2 yp = pp[bp][cy + 1][cx];
+        const double b = S.sp_scale_d * (hsxy[q] + sz2);
+        double2 td = helm(hpc[q], xm, xp, ym, yp, hpm[q], hp[st][q], S.h2inv_d, w2 * (double)hmr[st][q],
+                           -(S.omega_d * b));
+        if (hsrc[q] && zsrc) {
+          td.x -= S.alpha_c * pa.x;
+          td.y -= S.alpha_c * pa.y;
+        }
+        const double ae = (zok && hin[q]) ? af : 0.0;
+        const float2 rv = setup ? hr[st][q] : axpy2(hr[st][q], -ae, round2(td));
+        if (br >= 0) pl[br][hy[q]][hx[q]] = rv;
+      }
+    }
+    // p_k of plane zz+1 into the other buffer
+    const int bq = bp ^ 1;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      pp[bq][w * RY + j + 2][lane + 2] = rp[st][j];
+      pzm[j] = pzc[j];
+      pzc[j] = keep2(rp[st][j]);
+    }
+#pragma unroll
+    for (int q = 0; q < HS; ++q) {
+      if (tid + q * NT < NH) pp[bq][hy[q] + 1][hx[q] + 1] = hp[st][q];
+      hpm[q] = hpc[q];
+      hpc[q] = keep2(hp[st][q]);
+    }
+#pragma unroll
+    for (int q = 0; q < HS2; ++q)
+      if (tid + q * NT < NH2) pp[bq][gy2[q]][gx2[q]] = gp[st][q];
+  };
+
+  // prologue (raw set 0): p_k planes z0-2, z0-1 into registers (z0-1 also
+  // into LDS 0), then t / r_{k+1} of planes z0-1 (own rows), z0 (LDS 0) and
+  // z0+1 (LDS 1); then the raw sets of the first NS steps in flight
+  issue(0, C.z0 - 1, C.z0 - 2);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) pzc[j] = rp[0][j];
+#pragma unroll
+  for (int q = 0; q < HS; ++q) hpc[q] = hp[0][q];
+  issue(0, C.z0 - 1, C.z0 - 1);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    pp[0][w * RY + j + 2][lane + 2] = rp[0][j];
+    pzm[j] = pzc[j];
+    pzc[j] = rp[0][j];
+  }
+#pragma unroll
+  for (int q = 0; q < HS; ++q) {
+    if (tid + q * NT < NH) pp[0][hy[q] + 1][hx[q] + 1] = hp[0][q];
+    hpm[q] = hpc[q];
+    hpc[q] = hp[0][q];
+  }
+#pragma unroll
+  for (int q = 0; q < HS2; ++q)
+    if (tid + q * NT < NH2) pp[0][gy2[q]][gx2[q]] = gp[0][q];
+  issue(0, C.z0 - 1, C.z0);
+  __syncthreads();
+  float2 rm[RY], rc_[RY], rnx[RY];
+  tphase(0, C.z0 - 1, 0, -1);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) rm[j] = rnew[j];
+  issue(0, C.z0, C.z0 + 1);
+  __syncthreads();
+  tphase(0, C.z0, 1, 0);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) { rc_[j] = rnew[j]; mq0[j] = mq2[j]; }
+  issue(0, C.z0 + 1, C.z0 + 2);
+  __syncthreads();
+  tphase(0, C.z0 + 1, 0, 1);
+#pragma unroll
+  for (int j = 0; j < RY; ++j) { rnx[j] = rnew[j]; mq1[j] = mq2[j]; }
+  issue(0, C.z0 + 2, C.z0 + 3);
+  if constexpr (NS == 2) issue(NS - 1, C.z0 + 3, C.z0 + 4);
+  __syncthreads();
+
+  double acc = 0.0;
+  double2 sa = make_double2(0.0, 0.0);
+  int cur = 0, bp = 1;
+  // one plane of s; a step with z >= z1 (odd slab length) stores and sums nothing
+  auto step = [&](const int st, int z) __attribute__((always_inline)) {
+    const bool zin = z < C.z1;
+    const unsigned zbit = zin ? 0u : kOOB;
+    const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      const int ly = w * RY + j;
+      const float2 xm = pl[cur][ly + 1][lane];
+      const float2 xp = pl[cur][ly + 1][lane + 2];
+      const float2 ym = (j > 0) ? rc_[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
+      const float2 yp = (j < RY - 1) ? rc_[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
+      const double b = S.sp_scale_d * (sxy2[j] + sz2);
+      double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], S.h2inv_d, w2 * (double)mq0[j], S.omega_d * b);
+      if (rc.at(j, z - C.z0)) {  // receiver column of S^H: lambda r2 at the receiver cell
+        const int q = rc.take(S, j);
+        float2 r2 = ld2(r2v, q);
+        if (!setup) {
+          r2 = axpy2(r2, -af, ld2(t2v, q));
+          st2(r2v, q, r2);
+        }
+        sd.x += S.lam_d * r2.x;
+        sd.y += S.lam_d * r2.y;
+      }
+      const float2 s = round2(sd);
+      if (j == srcj && src_in_slab && z == sz) {
+        sa = make_double2(-S.alpha_c * (double)rc_[j].x, -S.alpha_c * (double)rc_[j].y);
+        acc += sa.x * sa.x + sa.y * sa.y;
+      }
+      const bool live = C.in[j] && zin;
+      const unsigned o8 = own_b(z, j) | zbit;
+      bst2(Rso, o8, s);
+      bst2(Rrn, o8, rc_[j]);
+      acc += live ? norm2d(s) : 0.0;
+    }
+    tphase(st, z + 2, bp, (cur + 2) % 3);
+    float2 rn2[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) rn2[j] = rnew[j];
+    __builtin_amdgcn_sched_barrier(0);
+    issue(st, z + 2 + NS, z + 3 + NS);
+    __syncthreads();
+    cur = (cur + 1) % 3;
+    bp ^= 1;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      rm[j] = rc_[j]; rc_[j] = rnx[j]; rnx[j] = rn2[j];
+      mq0[j] = mq1[j]; mq1[j] = mq2[j];
+    }
+  };
+  for (int z = C.z0; z < C.z1; z += 2) {
+    step(0, z);
+    step(NS - 1, z + 1);
+  }
+
+  const double tot = block_reduce<W>(acc, red);
+  if (tid == 0) part_s[S.slot_base + tile] = tot;
+  if (tile == 0 && tid == 0) T->iterA = k + 1;
+  if (srcj >= 0 && src_in_slab) T->sa = sa;
+}
+
+// ---------------------------------------------------------------------------
 // dispatch over the supported tile shapes
 // ---------------------------------------------------------------------------
 
 #define WRI_TILE_LIST(X) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(2, 8)
 
 bool cfg_supported(const TileCfg& c) {
-#define X(W_, R_) if (c.w == W_ && c.ry == R_) return c.tz >= 1 && c.tz <= 64 && (c.pf == 0 || c.pf == 1);
+#define X(W_, R_) if (c.w == W_ && c.ry == R_) return c.tz >= 1 && c.tz <= 64 && c.pf >= 0 && c.pf <= 3;
   WRI_TILE_LIST(X)
 #undef X
   return false;
@@ -1339,12 +1725,18 @@ hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const d
   const unsigned nb = (unsigned)nblocks;
 #define X(W_, R_)                                                                                   \
   if (c.w == W_ && c.ry == R_) {                                                                    \
-    if (c.pf && fwd_x_step(k))                                                                      \
-      hipLaunchKernelGGL((k_fwd_pf<W_, R_, 1>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d, \
-                         gd, ngroups);                                                              \
-    else if (c.pf)                                                                                  \
-      hipLaunchKernelGGL((k_fwd_pf<W_, R_, 0>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d, \
-                         gd, ngroups);                                                              \
+    if (c.pf == 1 && fwd_x_step(k))                                                                 \
+      hipLaunchKernelGGL((k_fwd_pf<W_, R_, 1, 0>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s,     \
+                         part_d, gd, ngroups);                                                      \
+    else if (c.pf == 1)                                                                             \
+      hipLaunchKernelGGL((k_fwd_pf<W_, R_, 0, 0>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s,     \
+                         part_d, gd, ngroups);                                                      \
+    else if (c.pf >= 2 && fwd_x_step(k))                                                            \
+      hipLaunchKernelGGL((k_fwd_pf<W_, R_, 1, 1>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s,     \
+                         part_d, gd, ngroups);                                                      \
+    else if (c.pf >= 2)                                                                             \
+      hipLaunchKernelGGL((k_fwd_pf<W_, R_, 0, 1>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s,     \
+                         part_d, gd, ngroups);                                                      \
     else                                                                                            \
       hipLaunchKernelGGL((k_fwd<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_s, part_d,     \
                          gd, ngroups);                                                              \
@@ -1361,8 +1753,14 @@ hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const d
   const unsigned nb = (unsigned)nblocks;
 #define X(W_, R_)                                                                                   \
   if (c.w == W_ && c.ry == R_) {                                                                    \
-    if (c.pf)                                                                                       \
+    if (c.pf == 1)                                                                                  \
       hipLaunchKernelGGL((k_adj_pf<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s,  \
+                         gd, ngroups, setup_only);                                                  \
+    else if (c.pf == 2)                                                                             \
+      hipLaunchKernelGGL((k_adj_rc<W_, R_, 1>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s, \
+                         gd, ngroups, setup_only);                                                  \
+    else if (c.pf == 3)                                                                             \
+      hipLaunchKernelGGL((k_adj_rc<W_, R_, 2>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s, \
                          gd, ngroups, setup_only);                                                  \
     else                                                                                            \
       hipLaunchKernelGGL((k_adj<W_, R_>), dim3(nb), dim3(64 * W_), 0, s, sys, st, part_d, part_s,     \

@@ -77,7 +77,9 @@ struct TileCfg {
   int w;       // wavefronts per workgroup
   int ry;      // rows per wavefront  (tile height TY = w*ry)
   int tz;      // z-slab length
-  int pf = 0;  // 1: software-pipelined z march (loads of plane z+2 in flight during plane z)
+  int pf = 0;  // 1: software-pipelined z march (loads of plane z+2 in flight during plane z);
+               // 2: pipelined, and the adjoint pass recomputes t = S p instead of reading it;
+               // 3: as 2, with the adjoint pass's loads two planes ahead
   int order = 0;  // 1: tile-major block order (see GroupDesc::tile_major)
   int ty() const { return w * ry; }
 };

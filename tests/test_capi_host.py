@@ -122,7 +122,7 @@ def test_validate_mode_and_iters():
     wide = (wri.WriGrid * 1)(wri.WriGrid(2000, 2000, 10, 0, 10.0, 1500.0))   # 4e6 cells in one plane
     assert L.wri_validate(wide, 1, None, 0, wri.KNOWN, 1) == wri.EINVAL
     assert "plane" in wri.last_error()
-    ok = (wri.WriGrid * 1)(wri.WriGrid(1958, 1958, 10, 0, 10.0, 1500.0))
+    ok = (wri.WriGrid * 1)(wri.WriGrid(1930, 1930, 10, 0, 10.0, 1500.0))
     assert L.wri_validate(ok, 1, None, 0, wri.KNOWN, 1) == wri.OK
 
 

@@ -411,7 +411,14 @@ def test_full_size_differentiation_workload():
 # --------------------------------------------------------------------------
 
 TILES = ["4,4,32,0,0", "4,4,32,1,1", "4,2,32,0,1", "4,2,32,1,1", "4,2,32,1,0", "4,2,16,0,0", "8,1,32,1,1",
-         "8,2,32,1,0", "2,8,32,0,0", "4,1,64,1,1", "8,1,32,1,2", "8,1,32,1,4", "4,2,32,1,2"]
+         "8,2,32,1,0", "2,8,32,0,0", "4,1,64,1,1", "8,1,32,1,2", "8,1,32,1,4", "4,2,32,1,2", "8,1,32,2,4",
+         "4,2,32,2,4", "4,4,32,2,4", "8,2,32,2,4", "8,1,32,2,0", "8,1,32,3,4", "4,2,32,3,4", "4,2,16,2,4",
+         "8,1,64,3,4"]
+
+# tiles whose adjoint pass recomputes t = S p_k, and a stored-t tile of the same shape
+RECOMPUTE_PAIRS = (("8,1,32,1,4", "8,1,32,2,4"), ("4,2,32,1,1", "4,2,32,2,4"), ("4,4,32,1,1", "4,4,32,2,4"),
+                   ("8,2,32,1,1", "8,2,32,2,4"), ("8,1,32,1,0", "8,1,32,2,0"), ("8,1,32,1,1", "8,1,32,3,4"),
+                   ("4,2,32,1,2", "4,2,32,3,4"))
 
 
 def test_large_workload_frequency_batch():
@@ -504,6 +511,45 @@ def test_block_orders_give_identical_bits(monkeypatch):
         for i in range(len(p.systems)):
             assert torch.equal(u[i], ref[0][i]), (t, i)
             assert res[i]["alpha"] == ref[1][i]["alpha"], (t, i)
+
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+def test_recomputed_t_gives_identical_bits(monkeypatch, mode):
+    """The adjoint pass that recomputes t = S p_k (pf = 2, 3) evaluates t with the
+    same stencil routine on the same stored p_k as the forward pass that stores
+    it, so the iterates are bit-identical to the stored-t path of the same tile
+    shape.  Sources sit on x/y tile edges, on the slab edge (z = 31 | 32) and in
+    both corners, so the source column of S enters the recomputed ring; a warm
+    start (r_0 = b - S u_0, then the set-up pass) is checked the same way."""
+    _say(f"recomputed t, {mode}")
+    p = wri_synth.custom_problem((150, 37, 45), nb=4, n_src=6, n_rec=20, seed=24, freqs=(7.0,), rtol=0.0)
+    g = p.grids[0]
+
+    def cell(x, y, z):
+        return (z * g.ny + y) * g.nx + x
+
+    for s, c in zip(p.systems, (cell(63, 7, 31), cell(64, 8, 32), cell(0, 0, 0), cell(149, 36, 44),
+                                cell(127, 16, 31), cell(128, 15, 32))):
+        s.src = c
+    outs = {}
+    for t in sorted({t for pair in RECOMPUTE_PAIRS for t in pair}):
+        monkeypatch.setenv("WRI_TILE", t)
+        b = wri.Batch(p, device=DEV, mode=mode)
+        u, res = wri.solve(b, max_iter=20)
+        if mode == "estimate":
+            b.set_alpha([0.5 * r["alpha"] for r in res])
+        u0 = [0.5 * x for x in u]
+        uw, rw = wri.solve(b, flags=wri.FLAG_WARM_START, u_out=u0, max_iter=6)
+        outs[t] = (u, res, uw, rw)
+    monkeypatch.delenv("WRI_TILE")
+    for a, c in RECOMPUTE_PAIRS:
+        ua, ra, uwa, rwa = outs[a]
+        uc, rc, uwc, rwc = outs[c]
+        for i in range(len(p.systems)):
+            assert torch.equal(ua[i], uc[i]), (a, c, i)
+            assert ra[i]["alpha"] == rc[i]["alpha"] and ra[i]["iters"] == rc[i]["iters"], (a, c, i)
+            assert torch.equal(uwa[i], uwc[i]), (a, c, i, "warm")
+            assert rwa[i]["alpha"] == rwc[i]["alpha"], (a, c, i, "warm")
 
 
 def test_uneven_workload_one_launch():
