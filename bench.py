@@ -35,7 +35,22 @@ HBM_PEAK_GBS = 8000.0
 #   forward k: read s, p_{k-1}, m; write p_k, t                          -> 36
 #              + on even k >= 2: read x, p_{k-2}; write x               -> +24
 #   adjoint k: read r_k, t, m; write r_{k+1}, s                         -> 36
-BYTES_NOTE = {"fwd": "36, +24 on even iterations (x update of two steps)", "adj": "36"}
+# Tiles with pf >= 2 recompute t = S p_k in the adjoint pass: the forward pass writes no t
+# (28, +24) and the adjoint pass reads p_k in its place (36).
+def bytes_note(pf):
+    if pf >= 2:
+        return {"fwd": "28, +24 on even iterations (x update of two steps); t is not stored",
+                "adj": "36 (reads p_k and recomputes t = S p_k)"}
+    return {"fwd": "36, +24 on even iterations (x update of two steps)", "adj": "36"}
+
+
+def kernel_label(dominant, pf):
+    if dominant == "fwd":
+        return "k_fwd_pf (fused forward CGLS stencil, t not stored)" if pf >= 2 else \
+               "k_fwd / k_fwd_pf (fused forward CGLS stencil)"
+    return "k_adj_rc (fused adjoint CGLS stencil, t recomputed)" if pf >= 2 else \
+           "k_adj / k_adj_pf (fused adjoint CGLS stencil)"
+
 
 # HBM traffic of one full-batch launch (48 systems x 128^3) from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, median over the launches of a 20-iteration
@@ -45,17 +60,14 @@ BYTES_NOTE = {"fwd": "36, +24 on even iterations (x update of two steps)", "adj"
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "02ef96444f5e3fa8",
+    "sources_sha256": "225f05abf655c3ea",
     "tiles": {
-        "8,1,32,1,4": {"fwd_x": {"fetch_kib": 1844253.8, "write_kib": 2359535.0},
-                       "fwd": {"fetch_kib": 1031510.2, "write_kib": 1573056.4},
-                       "adj": {"fetch_kib": 1010905.1, "write_kib": 1573099.3}},
-        "8,1,32,1,0": {"fwd_x": {"fetch_kib": 2018107.5, "write_kib": 2359560.2},
-                       "fwd": {"fetch_kib": 1199048.2, "write_kib": 1573086.1},
-                       "adj": {"fetch_kib": 1184879.9, "write_kib": 1573104.8}},
-        "4,2,32,1,0": {"fwd_x": {"fetch_kib": 2059830.9, "write_kib": 2359677.1},
-                       "fwd": {"fetch_kib": 1223818.1, "write_kib": 1573144.6},
-                       "adj": {"fetch_kib": 1245130.3, "write_kib": 1573206.2}},
+        "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1833340.8, "write_kib": 1573194.2},
+                       "fwd": {"fetch_kib": 1041794.1, "write_kib": 786708.2},
+                       "adj": {"fetch_kib": 1014818.2, "write_kib": 1573099.2}},
+        "4,2,32,2,4": {"fwd_x": {"fetch_kib": 1907028.3, "write_kib": 1573234.3},
+                       "fwd": {"fetch_kib": 1034372.9, "write_kib": 786665.8},
+                       "adj": {"fetch_kib": 1039999.0, "write_kib": 1573123.3}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
@@ -564,8 +576,7 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per full-batch launch",
                 "algorithmic_bytes_full_launch": round(fwd_full_bytes if dominant == "fwd" else adj_full_bytes),
-                "kernel": "k_fwd / k_fwd_pf (fused forward CGLS stencil)" if dominant == "fwd" else
-                          "k_adj / k_adj_pf (fused adjoint CGLS stencil)",
+                "kernel": kernel_label(dominant, kt["tile_pf"]),
                 "avg_launch_ms": round((kt["fwd_ms"] / kt["fwd_launches"]) if dominant == "fwd"
                                        else (kt["adj_ms"] / kt["adj_launches"]), 4),
                 "achieved_full_batch": round(ach_full, 1),
@@ -573,7 +584,7 @@ def main():
                 "avg_launch_ms_full_batch": round(fwd_full_ms if dominant == "fwd" else adj_full_ms, 4),
                 "fwd_gbs": round(fwd_gbs, 1), "adj_gbs": round(adj_gbs, 1),
                 "fwd_gbs_full_batch": round(fwd_full_gbs, 1), "adj_gbs_full_batch": round(adj_full_gbs, 1),
-                "bytes_per_cell": BYTES_NOTE, "tile": tile}
+                "bytes_per_cell": bytes_note(kt["tile_pf"]), "tile": tile}
 
     plain = None
     if not args.no_plain and args.plain_sample > 0:
