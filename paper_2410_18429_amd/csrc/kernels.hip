@@ -154,15 +154,15 @@ __device__ __forceinline__ float sponge_axis(int i, int n, int nb, float inv_nb)
 // sponge_axis_d, helm and round2 (the stencil arithmetic) live in stencil.hpp
 
 __device__ __forceinline__ float2 f2(float a, float b) { return make_float2(a, b); }
-// y + a x in float64 arithmetic, rounded once to complex float32
+// y + a x as one float64 fused multiply-add, rounded once to complex float32
 __device__ __forceinline__ float2 axpy2(float2 y, double a, float2 x) {
-  return f2((float)((double)y.x + a * (double)x.x), (float)((double)y.y + a * (double)x.y));
+  return f2((float)fma(a, (double)x.x, (double)y.x), (float)fma(a, (double)x.y, (double)y.y));
 }
 // x + c2 p2 + c1 p1 in float64 arithmetic, rounded once (the x update that
-// takes two CGLS steps at a time; with c2 = 0 it equals axpy2(x, c1, p1))
+// takes two CGLS steps at a time; with c2 = 0 and finite p2 it equals axpy2(x, c1, p1))
 __device__ __forceinline__ float2 xupd2(float2 x, double c2, float2 p2, double c1, float2 p1) {
-  return f2((float)(((double)x.x + c2 * (double)p2.x) + c1 * (double)p1.x),
-            (float)(((double)x.y + c2 * (double)p2.y) + c1 * (double)p1.y));
+  return f2((float)fma(c1, (double)p1.x, fma(c2, (double)p2.x, (double)x.x)),
+            (float)fma(c1, (double)p1.y, fma(c2, (double)p2.y, (double)x.y)));
 }
 __device__ __forceinline__ double norm2d(float2 v) {
   return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
