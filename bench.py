@@ -60,14 +60,14 @@ def kernel_label(dominant, pf):
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "225f05abf655c3ea",
+    "sources_sha256": "eb8bda0340f74e73",
     "tiles": {
-        "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1833340.8, "write_kib": 1573194.2},
-                       "fwd": {"fetch_kib": 1041794.1, "write_kib": 786708.2},
-                       "adj": {"fetch_kib": 1014818.2, "write_kib": 1573099.2}},
-        "4,2,32,2,4": {"fwd_x": {"fetch_kib": 1907028.3, "write_kib": 1573234.3},
-                       "fwd": {"fetch_kib": 1034372.9, "write_kib": 786665.8},
-                       "adj": {"fetch_kib": 1039999.0, "write_kib": 1573123.3}},
+        "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1842277.7, "write_kib": 1573194.8},
+                       "fwd": {"fetch_kib": 1047779.5, "write_kib": 786706.3},
+                       "adj": {"fetch_kib": 1032439.0, "write_kib": 1573111.5}},
+        "4,2,32,2,4": {"fwd_x": {"fetch_kib": 1909017.8, "write_kib": 1573229.9},
+                       "fwd": {"fetch_kib": 1039976.3, "write_kib": 786673.1},
+                       "adj": {"fetch_kib": 1054648.9, "write_kib": 1573149.4}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
