@@ -427,7 +427,11 @@ typedef struct {
   double  fwd_bytes_full, adj_bytes_full;
   int32_t tile_w, tile_ry, tile_tz, tile_pf, tile_order; /* tile shape of the fused launches
                                                            (waves, rows per wave, z-slab,
-                                                           pipelined, tile-major order)  */
+                                                           march: 0 plain, 1 pipelined,
+                                                           2 pipelined with t recomputed
+                                                           in the adjoint pass, 3 as 2 with
+                                                           two planes of prefetch; block
+                                                           order)                        */
   int32_t reserved_;
 } wri_timing;
 
