@@ -60,7 +60,7 @@ def kernel_label(dominant, pf):
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "eb8bda0340f74e73",
+    "sources_sha256": "1fde0396a50c26bc",
     "tiles": {
         "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1842277.7, "write_kib": 1573194.8},
                        "fwd": {"fetch_kib": 1047779.5, "write_kib": 786706.3},

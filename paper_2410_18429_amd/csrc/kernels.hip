@@ -1325,6 +1325,19 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 // ---------------------------------------------------------------------------
 // fused adjoint kernel with t recomputed: the forward pass stores no t
 // ---------------------------------------------------------------------------
+
+// A register copy the compiler cannot coalesce with its source: a loaded
+// register that is kept for later planes is copied out once it has been used,
+// so the load's own register dies there and the next load of the march can
+// land in it (a coalesced copy keeps it alive, and the next load then goes to
+// a fresh register that has to be copied, with a wait, at the loop back-edge).
+__device__ __forceinline__ float keep1(float v) {
+  float r;
+  asm("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
+  return r;
+}
+__device__ __forceinline__ float2 keep2(float2 v) { return make_float2(keep1(v.x), keep1(v.y)); }
+
 // r_{k+1} = r_k - a_k t is needed on the tile and on a one-cell ring around it
 // (the stencil of s = A^H r_{k+1}), so t = S p_k is evaluated there, which
 // takes p_k on a two-cell ring.  t comes from the same stencil routine, with
@@ -1338,22 +1351,10 @@ k_adj_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 // then t and r_{k+1} of plane z+2 on tile + ring 1 from the p_k plane z+2 (LDS,
 // two rings) and the p_k planes z+1, z+3 (registers); then p_k of plane z+3 is
 // committed to the other LDS buffer and the loads of plane z+2+NS (r_k, m) and
-// z+3+NS (p_k) are issued into raw register set NS: with NS = 2 the sets
-// alternate between even and odd steps, so a load has two steps to arrive (at
-// the cost of registers, i.e. of resident waves).  A loaded register is
-// consumed where it lands and never copied while in flight.
-// A register copy the compiler cannot coalesce with its source: a loaded
-// register that is kept for later planes is copied out once it has been used,
-// so the load's own register dies there and the next load of the march can
-// land in it (a coalesced copy keeps it alive, and the next load then goes to
-// a fresh register that has to be copied, with a wait, at the loop back-edge).
-__device__ __forceinline__ float keep1(float v) {
-  float r;
-  asm("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
-  return r;
-}
-__device__ __forceinline__ float2 keep2(float2 v) { return make_float2(keep1(v.x), keep1(v.y)); }
-
+// z+3+NS (p_k) are issued.  There are NS sets of raw load registers: with
+// NS = 2 even and odd steps use their own set, so a load has two steps to
+// arrive (at the cost of registers, i.e. of resident waves).  A loaded register
+// is consumed where it lands and never copied while in flight.
 template <int W, int RY, int NS>
 __global__ void __launch_bounds__(64 * W)
 k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const double* __restrict__ part_d,
