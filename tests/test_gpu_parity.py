@@ -301,6 +301,22 @@ def test_degenerate_grids(shape):
     assert rel(_np(u[0]), ref["u"][0]) < 1e-4
 
 
+@pytest.mark.parametrize("tile", ["4,4,32,2,4", "8,1,32,3,4", "4,2,16,2,4"])
+def test_degenerate_grids_recomputed_t(monkeypatch, tile):
+    """The recomputed-t march on grids of one plane, one row, one column and a
+    ragged slab (z-slab 16 over 33 planes: slabs of 16, 16 and 1), against the
+    oracle; every ring cell and plane beyond the grid must read as zero."""
+    monkeypatch.setenv("WRI_TILE", tile)
+    for shape, nb in [((3, 2, 1), 0), ((1, 1, 5), 0), ((64, 1, 3), 0), ((65, 17, 2), 0), ((70, 9, 33), 2)]:
+        _say(f"degenerate {shape}, tile {tile}")
+        p = wri_synth.custom_problem(shape, nb=nb, n_src=1, n_rec=min(3, shape[2]), seed=16, rtol=1e-6,
+                                     mode="known")
+        ref = oracle.objective_grad(p)
+        u, res = wri.solve(wri.Batch(p, device=DEV))
+        assert res[0]["status"] in ("converged",), (shape, tile)
+        assert rel(_np(u[0]), ref["u"][0]) < 1e-4, (shape, tile)
+
+
 def test_nan_model_reports_breakdown():
     _say("nan model")
     p = wri_synth.custom_problem((20, 10, 8), nb=2, n_src=2, n_rec=5, seed=17)
