@@ -180,6 +180,39 @@ def factor(M):
     return spl.splu(sp.csc_matrix(M), permc_spec="COLAMD")
 
 
+class NormalInverse:
+    """x = N^{-1} y for N = A^H A + lam^2 P^H P, through the LU factors of A
+    instead of a factor of N (A is a 7-point operator; N has a 25-point
+    pattern and far more fill, so this route reaches larger grids).
+
+    With B = (A^H A)^{-1} = A^{-1} A^{-H}, the Sherman-Morrison-Woodbury
+    identity for the rank-n_r update lam^2 P^H P gives
+        N^{-1} = B - B P^H (lam^{-2} I + P B P^H)^{-1} P B,
+    where B P^H takes 2 n_r solves with the factors of A and the middle
+    matrix is n_r x n_r.  lam = 0 or no receivers leaves N^{-1} = B.
+    Same interface as a SuperLU factor of N (`solve`)."""
+
+    def __init__(self, A, P, lam):
+        self.lu = spl.splu(sp.csc_matrix(A), permc_spec="MMD_AT_PLUS_A")
+        self.P = sp.csr_matrix(P)
+        self.Z = None
+        nr = P.shape[0]
+        if lam != 0.0 and nr > 0:
+            PH = self.P.conj().T.toarray()                 # n x n_r
+            self.Z = self._B(PH)                           # B P^H
+            M = np.eye(nr) / lam ** 2 + self.P @ self.Z    # lam^-2 I + P B P^H
+            self.M = M
+
+    def _B(self, y):
+        return self.lu.solve(self.lu.solve(y, trans="H"))
+
+    def solve(self, y):
+        x = self._B(np.asarray(y, dtype=np.complex128))
+        if self.Z is not None:
+            x = x - self.Z @ np.linalg.solve(self.M, self.P @ x)
+        return x
+
+
 def solve_known(A, P, lam, alpha, e, d, lu=None) -> np.ndarray:
     """u = argmin ||A u - alpha e||^2 + lam^2 ||P u - d||^2
        = (A^H A + lam^2 P^H P)^{-1} (A^H (alpha e) + lam^2 P^H d)."""
@@ -239,8 +272,13 @@ def gradient_term(omega, u, A, alpha, e) -> np.ndarray:
 
 
 def objective_grad(problem, m_list=None, mode=None, route="varpro", b_list=None,
-                   return_fields=True) -> Dict:
+                   return_fields=True, normal_solver="factor_N") -> Dict:
     """Exact variable-projection objective and gradient over all systems.
+
+    normal_solver: "factor_N" (SuperLU of N = A^H A + lam^2 P^H P) or
+    "woodbury" (`NormalInverse`, through the LU of A; for grids where the fill
+    of N is too large).  The "augmented" and "projected" routes always factor
+    their own matrices.
 
     Returns dict(J, J_sys, g (list per grid, float64 (nz,ny,nx)), u (list),
     alpha (array))."""
@@ -257,7 +295,13 @@ def objective_grad(problem, m_list=None, mode=None, route="varpro", b_list=None,
         if key not in cache:
             A = helmholtz(g, m_list[s.grid], s.omega, b)
             P = restriction(g.n, s.rec)
-            cache = {key: (A, P, factor(normal_matrix(A, P, s.lam)))}
+            if normal_solver == "woodbury":
+                inv = NormalInverse(A, P, s.lam)
+            elif normal_solver == "factor_N":
+                inv = factor(normal_matrix(A, P, s.lam))
+            else:
+                raise ValueError(normal_solver)
+            cache = {key: (A, P, inv)}
         A, P, lu = cache[key]
         e = unit_vector(g.n, s.src)
         if mode == KNOWN:
@@ -502,11 +546,16 @@ def lbfgs_two_loop(g: np.ndarray, pairs, h0: float) -> np.ndarray:
     return r
 
 
-def inexact_objective_grad(problem, m, rtol, mode=None, alpha_scale=None):
+def inexact_objective_grad(problem, m, rtol, mode=None, alpha_scale=1.0):
     """J and g at model m with every system solved by the reference CGLS to
     the relative normal-residual tolerance rtol (complex128).  J and g use the
     recurred residual r1 = b1 - (A u - alpha e) of CGLS, as the GPU path does:
-    J = sum ||r||^2, g = -sum 2 omega^2 Re(conj(u) r1)."""
+    J = sum ||r||^2, g = -sum 2 omega^2 Re(conj(u) r1).
+
+    alpha_scale is the weight c of the source column of S = [[A, -c e],
+    [lam P, 0]] in ESTIMATE mode; the default 1 is S as eq. SimpObj prints it.
+    Any c > 0 has the same minimiser but different iterates, so a caller that
+    compares iterates with a solver using another column weight passes it."""
     mode = mode or problem.mode
     J = 0.0
     grads = [np.zeros(gr.n) for gr in problem.grids]
@@ -515,8 +564,8 @@ def inexact_objective_grad(problem, m, rtol, mode=None, alpha_scale=None):
         gr = problem.grids[s.grid]
         A = helmholtz(gr, m[s.grid], s.omega)
         P = restriction(gr.n, s.rec)
-        c = (np.sqrt(42.0) / gr.h ** 2) if alpha_scale is None else alpha_scale
-        out = cgls(A, P, s.lam, s.src, mode, s.alpha, s.d, rtol=rtol, maxiter=10 ** 6, alpha_scale=c)
+        out = cgls(A, P, s.lam, s.src, mode, s.alpha, s.d, rtol=rtol, maxiter=10 ** 6,
+                   alpha_scale=float(alpha_scale))
         r = out["r"]
         J += float(np.vdot(r, r).real)
         grads[s.grid] += -2.0 * s.omega ** 2 * np.real(np.conj(out["u"]) * r[:gr.n])
@@ -526,7 +575,8 @@ def inexact_objective_grad(problem, m, rtol, mode=None, alpha_scale=None):
 
 def awri(problem, m0, gamma: float, eps0: float, n_outer: int, memory: int = 5, eps_tv: float = 1e-9,
          step0: float = 0.01, eps_min: float = 1e-8, solver: str = "exact", m_min: float = 0.0,
-         m_max: float = 0.0, max_step: float = 0.0, mask_sponge: bool = False) -> Dict:
+         m_max: float = 0.0, max_step: float = 0.0, mask_sponge: bool = False,
+         alpha_scale: float = 1.0) -> Dict:
     """Algorithm 2 (source-free AWRI with TV) on a single-grid problem.
 
     Objective F(m) = J(m) + gamma * TV(m) in this package's scaling
@@ -549,7 +599,8 @@ def awri(problem, m0, gamma: float, eps0: float, n_outer: int, memory: int = 5, 
     is an extension of the physical model rather than part of it.
 
     solver: "exact" (sparse direct, eps only drives the schedule) or "cgls"
-    (reference CGLS to tolerance eps, see `inexact_objective_grad`).
+    (reference CGLS to tolerance eps, see `inexact_objective_grad`, with the
+    source-column weight alpha_scale).
     Returns dict(m, history) with one record per trial:
     (F, J, TV, eps, accepted, solver iterations)."""
     grid = problem.grids[0]
@@ -561,7 +612,7 @@ def awri(problem, m0, gamma: float, eps0: float, n_outer: int, memory: int = 5, 
             o = objective_grad(problem, [mm.reshape(grid.shape)], return_fields=False)
             J, g, it = o["J"], o["g"][0].reshape(-1), 0
         else:
-            J, gl, its = inexact_objective_grad(problem, [mm], eps)
+            J, gl, its = inexact_objective_grad(problem, [mm], eps, alpha_scale=alpha_scale)
             g, it = gl[0], int(sum(its))
         t = tv(grid, mm, eps_tv)
         gg = g + gamma * tv_grad(grid, mm, eps_tv)

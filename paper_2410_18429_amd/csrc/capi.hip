@@ -576,11 +576,20 @@ int autotune(Ctx& C) {
   return set_config(C, best_cfg);
 }
 
+// A captured chunk bakes in every kernel argument of its launches: the tile
+// (template and grid size), the group count and the five table pointers.  The
+// table pointers are workspace offsets that depend on every grid's cell count,
+// the number of grids and the receiver sets, so two batches that share the
+// workspace base and the tile can still place them differently; the key holds
+// the pointers themselves, not only the base.
 std::string graph_key(const Ctx& C, int64_t k0, int chunk) {
   std::string k;
-  char buf[128];
+  char buf[256];
   // the kernels of a chunk depend on k0 only through fwd_x_step(k0 + i)
-  snprintf(buf, sizeof(buf), "%d|%p|%d|%d|%d|", C.dev, (void*)C.ws, chunk, (int)(k0 & 1), k0 >= 2 ? 1 : (int)k0);
+  snprintf(buf, sizeof(buf), "%d|%d|%d|%d|", C.dev, chunk, (int)(k0 & 1), k0 >= 2 ? 1 : (int)k0);
+  k += buf;
+  snprintf(buf, sizeof(buf), "%p,%p,%p,%p,%p,%d|", (const void*)C.dsys, (const void*)C.dstate,
+           (const void*)C.part_s, (const void*)C.part_d, (const void*)C.dgd, (int)C.hgd.size());
   k += buf;
   const TileCfg& c = cur_cfg(C);
   snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d;", c.w, c.ry, c.tz, c.pf, c.order, C.nblocks);

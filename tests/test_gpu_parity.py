@@ -128,6 +128,63 @@ def test_solve_parity_exact(shape, mode):
     assert rel(g, ref["g"][0].reshape(-1)) < 1e-3
 
 
+_MULTI_SLAB_REF = {}
+
+
+def _multi_slab_problem():
+    """70 x 20 x 67: two x-tiles of 64 lanes (the second ragged), two or three
+    y-tiles (16- or 8-row tiles) and three z-slabs of 32 planes (the last of
+    3) or five of 16; the second source of each frequency sits at x = 64,
+    y = 16, z = 32, on an x-tile, y-tile and slab boundary at once."""
+    p = wri_synth.custom_problem((70, 20, 67), nb=6, n_src=2, n_rec=10, seed=7, freqs=(6.0, 9.0),
+                                 rtol=PARITY_RTOL)
+    g = p.grids[0]
+    edge = (32 * g.ny + 16) * g.nx + 64
+    for i, s in enumerate(p.systems):
+        if i % 2 == 1:
+            s.src = edge
+    return p
+
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+def test_solve_parity_production_tiles_multi_slab(monkeypatch, mode):
+    """Converged solves on the recomputed-t tiles the autotuner picks for the
+    large workloads, on a grid of several x-tiles, y-tiles and z-slabs, against
+    the exact minimiser (the oracle's Woodbury route through the factors of A):
+    u, alpha, J within 1e-4, the gradient within 1e-3 in norm and element-wise
+    relative to its largest entry.  A complex64-storage CGLS on the CPU reaches
+    7e-6 on u here at this rtol."""
+    p = _multi_slab_problem()
+    if mode not in _MULTI_SLAB_REF:
+        _say(f"multi-slab oracle, mode={mode}")
+        _MULTI_SLAB_REF[mode] = oracle.objective_grad(p, mode=mode, normal_solver="woodbury")
+    ref = _MULTI_SLAB_REF[mode]
+    gref = ref["g"][0].reshape(-1)
+    for tile in ("4,4,32,2,4", "4,2,16,2,4"):
+        monkeypatch.setenv("WRI_TILE", tile)
+        _say(f"multi-slab 70x20x67 mode={mode} tile={tile}")
+        b = wri.Batch(p, device=DEV, mode=mode)
+        J, grads, res = wri.objective_grad(b, max_iter=60000)
+        u, res_u = wri.solve(b, max_iter=60000)
+        g = grads[0].cpu().numpy().astype(np.float64)
+        eg = rel(g, gref)
+        eg_max = float(np.abs(g - gref).max() / np.abs(gref).max())
+        for i in range(len(p.systems)):
+            eu = rel(_np(u[i]), ref["u"][i])
+            ea = abs(res_u[i]["alpha_ls"] - ref["alpha"][i]) / abs(ref["alpha"][i])
+            eJ = abs(res[i]["J"] - ref["J_sys"][i]) / ref["J_sys"][i]
+            _say(f"  sys {i}: iters {res[i]['iters']} u err {eu:.2e} alpha err {ea:.2e} J err {eJ:.2e}")
+            assert res[i]["status"] == "converged", (tile, res[i])
+            assert eu < 1e-4, (tile, i)
+            assert eJ < 1e-4, (tile, i)
+            if mode == "estimate":
+                assert ea < 1e-4, (tile, i)
+                assert abs(res_u[i]["alpha"] - ref["alpha"][i]) < 1e-4 * abs(ref["alpha"][i]), (tile, i)
+        _say(f"  J err {abs(J - ref['J']) / ref['J']:.2e} g err {eg:.2e} (max entry {eg_max:.2e})")
+        assert abs(J - ref["J"]) < 1e-4 * ref["J"]
+        assert eg < 1e-3 and eg_max < 1e-3, (tile, eg, eg_max)
+
+
 def test_tiny_config_both_modes():
     _say("tiny config")
     p = wri_synth.make_config("tiny", data="none")
@@ -187,6 +244,31 @@ def test_graph_and_eager_agree():
             assert rg[i]["iters"] == re_[i]["iters"]
 
 
+def test_shared_workspace_across_batch_shapes():
+    """Two batches of the same tile count and launch size (70x37x32 and
+    70x37x30: one z-slab each at the default tile) on one workspace buffer.
+    Their table offsets inside the workspace differ (the gradient partials
+    depend on the cell count), so a graph captured for the first must not be
+    replayed for the second.  Each result must equal the same solve on a
+    workspace of its own, bit for bit, also when the first shape comes back."""
+    _say("shared workspace, 70x37x32 then 70x37x30")
+    pa = wri_synth.custom_problem((70, 37, 32), nb=3, n_src=2, n_rec=8, seed=31, freqs=(7.0,), rtol=1e-5)
+    pb = wri_synth.custom_problem((70, 37, 30), nb=3, n_src=2, n_rec=8, seed=31, freqs=(7.0,), rtol=1e-5)
+    fresh = {}
+    for name, p in (("a", pa), ("b", pb)):
+        fresh[name] = wri.solve(wri.Batch(p, device=DEV))
+    ba, bb = wri.Batch(pa, device=DEV), wri.Batch(pb, device=DEV)
+    ws = ba.workspace(ba.mode, 0)
+    assert ws.numel() >= bb.workspace(bb.mode, 0).numel()
+    bb._ws[(bb.mode, 0)] = ws          # the second batch runs on the first one's buffer
+    for rep, (name, b) in enumerate((("a", ba), ("b", bb), ("a", ba), ("b", bb))):
+        u, res = wri.solve(b)
+        uf, rf = fresh[name]
+        for i in range(len(u)):
+            assert res[i]["iters"] == rf[i]["iters"], (rep, name, i)
+            assert torch.equal(u[i], uf[i]), (rep, name, i)
+
+
 def _uneven_problem():
     """Three grids of different sizes in one batch, per-system tolerances."""
     rng = np.random.default_rng(11)
@@ -200,7 +282,7 @@ def _uneven_problem():
         mt += q.m_true
         for s in q.systems:
             s.grid = gi
-            s.rtol = float(10.0 ** (-2 - 4 * rng.uniform()))
+            s.rtol = float(10.0 ** (-2 - 3 * rng.uniform()))   # the workloads' range 1e-2 .. 1e-5
             systems.append(s)
     return wri_synth.Problem("uneven-small", grids, m, mt, systems)
 
@@ -217,20 +299,29 @@ def test_uneven_grids_adaptive_tolerances():
         ref = oracle.cgls(A, P, s.lam, s.src, "estimate", 0, s.d.astype(np.complex64).astype(np.complex128),
                           rtol=s.rtol, maxiter=100000, alpha_scale=wri.alpha_scale(p.grids[s.grid].h))
         assert res[i]["status"] == "converged" and res[i]["relres"] <= s.rtol
-        assert abs(res[i]["iters"] - ref["iters"]) <= max(2, 0.1 * ref["iters"]), (res[i]["iters"], ref["iters"])
-        # float64 true normal residual of the GPU iterate, against the floor set
-        # by storing the exact minimiser in complex64.  CGLS with complex64
-        # vectors levels off at a multiple of that floor that grows with the
-        # conditioning of S (the recurred residual keeps falling, the true one
-        # does not): on these systems a float32-storage CGLS run on the CPU
-        # with the same updates lands at 3x (system 1) to 22x (system 5) the
-        # floor, so tolerances below the floor are met in the recurred sense only.
+        # float64 true normal residual of the GPU iterate against tau32, the
+        # true residual that the oracle's CGLS reaches at the same rtol when it
+        # stores its vectors in complex64 as the GPU does (same column weight).
+        # The recurred residual keeps falling below the float32 storage floor
+        # and the true one does not, so below that floor a tolerance is met in
+        # the recurred sense only; measured on these systems tau32 is 1.0-1.4x
+        # rtol for rtol >= 1e-4 and 18x at 1.6e-5.  The true residual is taken
+        # with the unscaled source column, which weighs the alpha component
+        # 1/c more than the solver's stopping test; hence the 2 rtol.
         tr = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d, _np(u[i]), res[i]["alpha"])
-        ue, ae = oracle.solve_estimate(A, P, s.lam, s.src, s.d)
-        floor = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d,
-                                       ue.astype(np.complex64).astype(np.complex128), ae)
-        _say(f"  sys {i}: rtol {s.rtol:.1e} true normal residual {tr:.2e} (c64 floor {floor:.2e})")
-        assert tr <= max(2 * s.rtol, 50 * floor), (tr, s.rtol, floor)
+        emu = oracle.cgls(A, P, s.lam, s.src, "estimate", 0, s.d.astype(np.complex64).astype(np.complex128),
+                          rtol=s.rtol, maxiter=100000, vec_dtype=np.complex64,
+                          alpha_scale=wri.alpha_scale(p.grids[s.grid].h))
+        tau32 = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d,
+                                       emu["u"].astype(np.complex128), emu["alpha"])
+        _say(f"  sys {i}: rtol {s.rtol:.1e} iters {res[i]['iters']} (c128 {ref['iters']}, c64 {emu['iters']}) "
+             f"true normal residual {tr:.2e} (tau32 {tau32:.2e})")
+        assert tr <= max(2 * s.rtol, 3 * tau32), (tr, s.rtol, tau32)
+        # iteration count against the same CGLS with complex64 storage (the
+        # GPU's precision; measured within one iteration on every system);
+        # complex128 storage needs up to 10 % fewer (39 against 43 on system 4)
+        assert abs(res[i]["iters"] - emu["iters"]) <= max(2, 0.05 * emu["iters"]), (res[i]["iters"], emu["iters"])
+        assert res[i]["iters"] >= ref["iters"] - 2, (res[i]["iters"], ref["iters"])
 
 
 # --------------------------------------------------------------------------
@@ -406,7 +497,9 @@ def test_full_size_differentiation_workload():
         tr = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d, uk, res_u[k]["alpha"])
         _say(f"  sys {k}: J gpu {res[k]['J']:.6e} oracle(u,alpha) {t1 + t2:.6e} true normal residual {tr:.2e}")
         assert abs(res[k]["J"] - (t1 + t2)) <= 1e-3 * (t1 + t2)
-        assert tr <= 1e-3
+        # 2 rtol (the stopping test weighs the source column by c, this one
+        # does not); measured 9.8e-5 .. 1.0e-4 on these systems
+        assert tr <= 2e-4
         # source-weight stationarity holds exactly for alpha_ls = (A u)[src]
         assert abs((A @ uk)[s.src] - res_u[k]["alpha_ls"]) <= 1e-5 * abs(res_u[k]["alpha_ls"])
     # gradient at the 20 largest cells, recomputed in float64 from all 48 (u, alpha)
@@ -419,7 +512,9 @@ def test_full_size_differentiation_workload():
         gref += 2 * s.omega ** 2 * np.real(np.conj(uk[flat]) * rows)
     err = np.abs(g.reshape(-1)[flat] - gref) / np.abs(gref).max()
     _say(f"  gradient at top-20 cells: max rel deviation {err.max():.2e}")
-    assert err.max() < 2e-2
+    # measured 7.2e-6: float32 storage of u and of the recurred r1 against the
+    # float64 recomputation from the stored u
+    assert err.max() < 1e-4
 
 
 # --------------------------------------------------------------------------
@@ -728,8 +823,8 @@ def test_operator_adjoint_identity():
 def test_full_size_directional_derivative():
     """128^3, 48 systems, rtol 1e-4: the central difference of the GPU
     objective along a smooth model perturbation (a Gaussian bump of 5 % of m,
-    sigma 12 cells) matches g . dm from the gradient kernel to 2 % (measured
-    0.45 %).  With a 0.5 % bump the change of J, 1e-4 of J, is within 5 % of
+    sigma 12 cells) matches g . dm from the gradient kernel to 1 % (measured
+    0.45 % and 0.57 % on two boxes).  With a 0.5 % bump the change of J, 1e-4 of J, is within 5 % of
     the ~6e-6 scatter that the rtol-1e-4 solves leave in J; for the same
     reason the Taylor remainder (second order, below 4e-6 here) is not
     resolved at this size — it is checked on the oracle."""
@@ -749,4 +844,4 @@ def test_full_size_directional_derivative():
         Js[t], _, _ = wri.objective_grad(b)
     fd = (Js[1.0] - Js[-1.0]) / 2.0
     _say(f"  J0 {J0:.8e}  g.dm {gd:.6e}  central difference {fd:.6e}")
-    assert abs(fd - gd) <= 2e-2 * abs(gd)
+    assert abs(fd - gd) <= 1e-2 * abs(gd)

@@ -96,6 +96,70 @@ def test_sponge_zero_inside_and_damps():
         assert np.vdot(u, A @ u).imag < 0.0
 
 
+def test_sponge_values_at_named_cells():
+    """Values of the damping reading b = (2 d0 / v_ref^2) sum_axes (delta/nb)^2,
+    d0 = 3 v_ref ln(1000) / (2 nb h), worked out by hand for nb = 3, h = 10 m,
+    v_ref = 1500 m/s:  d0 = 3*1500*ln(1000)/60 = 225 ln 10, so
+    2 d0 / v_ref^2 = 450 ln 10 / 2.25e6 = 2e-4 ln 10.  On a 12 x 11 x 10 grid the
+    depth into the sponge along an axis of n cells is 3, 2, 1 at i = 0, 1, 2 and
+    at i = n-1, n-2, n-3, and 0 for 3 <= i <= n-4 (the sponge is nb cells thick;
+    an off-by-one such as nb-1-i or a wrong d0 constant fails here)."""
+    g = Grid(12, 11, 10, 10.0, 3, 1500.0)
+    b = oracle.sponge(g).reshape(g.shape)      # (z, y, x)
+    k = 2e-4 * np.log(10.0)
+    interior = (5, 5, 5)
+    cases = {
+        # (z, y, x): sum of (delta/3)^2 over the three axes
+        (5, 5, 0): 1.0,                 # x-face, outermost cell (depth 3)
+        (5, 5, 1): 4.0 / 9.0,           # depth 2
+        (5, 5, 2): 1.0 / 9.0,           # depth 1
+        (5, 5, 3): 0.0,                 # first interior cell next to the x-face
+        (5, 5, 11): 1.0,                # opposite x-face (n = 12: i = 11, 10, 9, 8)
+        (5, 5, 10): 4.0 / 9.0,
+        (5, 5, 9): 1.0 / 9.0,
+        (5, 5, 8): 0.0,
+        (5, 0, 5): 1.0,                 # y-face
+        (5, 8, 5): 1.0 / 9.0,           # n = 11: depth 1 at i = 8
+        (5, 7, 5): 0.0,
+        (9, 5, 5): 1.0,                 # z-face, n = 10: depth 3 at i = 9
+        (6, 5, 5): 0.0,
+        (5, 0, 0): 2.0,                 # x-y edge, both depth 3
+        (0, 1, 2): 1.0 + 4.0 / 9.0 + 1.0 / 9.0,   # corner region, depths 3 (z), 2 (y), 1 (x)
+        (0, 0, 0): 3.0,                 # corner
+        (9, 10, 11): 3.0,               # opposite corner
+        interior: 0.0,
+    }
+    for (z, y, x), q in cases.items():
+        assert abs(b[z, y, x] - k * q) <= 1e-14 * k, ((z, y, x), b[z, y, x], k * q)
+
+
+def test_sponge_round_trip_attenuation_is_one_in_a_thousand():
+    """Independent route to the sponge constant: b = 2 d / v^2 turns the damped
+    wave equation u_tt + 2 d u_t = v^2 Lap u into A = Lap + omega^2 m - i omega b
+    (m = 1/v^2, transform with exp(-i omega t)), so d is an amplitude decay rate
+    per second.  A plane wave crossing the layer and coming back loses
+    exp(-2 int d dx / v); the quadratic profile d(x) = d0 (x/L)^2 with
+    d0 = 3 v ln(1000) / (2 L) gives int d dx = d0 L / 3, a round-trip factor of
+    exactly 1e-3.  The cell sum of the oracle's values (depths 1..nb, cell width
+    h, L = nb h) approaches that integral as nb grows (midpoint-like error
+    O(1/nb))."""
+    v = 1500.0
+    ratio = {}
+    for nb in (50, 100, 200):
+        g = Grid(2 * nb + 2, 1, 1, 7.5, nb, v)
+        b = oracle.sponge(g).reshape(-1)
+        # along x only; y and z have one cell each (the sponge of the thin
+        # axes is the same constant in every cell and cancels below)
+        bx = b - b[nb]                      # cell nb is the first interior cell along x
+        d = bx[:nb] * v ** 2 / 2.0          # decay rate per cell, depths nb..1
+        factor = np.exp(-2.0 * np.sum(d) * g.h / v)
+        ratio[nb] = np.log(factor) / np.log(1e-3)
+        assert abs(ratio[nb] - 1.0) < 2.0 / nb, (nb, ratio[nb])
+    # the cell sum converges to the integral at first order in 1/nb: one
+    # Richardson step removes that term and must land on the design value
+    assert abs(2.0 * ratio[200] - ratio[100] - 1.0) < 1e-3, ratio
+
+
 def test_point_source_is_outgoing_wave():
     """Convention pin (the paper's source tables use exp(-i 2 pi f t0), i.e.
     forward transform with exp(-i omega t)).  Under that convention an
@@ -802,3 +866,42 @@ def test_offgrid_gradient_matches_central_differences():
         fd = (oracle.objective_grad_offgrid(p, src, rec, m_list=[mp.reshape(p.grids[0].shape)])["J"] -
               oracle.objective_grad_offgrid(p, src, rec, m_list=[mn.reshape(p.grids[0].shape)])["J"]) / (2 * step)
         assert abs(fd - g[c]) <= 1e-6 * np.abs(g).max(), (c, fd, g[c])
+
+
+# --------------------------------------------------------------------------
+# N^{-1} through the factors of A (Sherman-Morrison-Woodbury route)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lam,n_rec", [(0.12, 9), (3.0, 1), (0.0, 6), (0.5, 0)])
+def test_normal_inverse_through_factors_of_A(lam, n_rec):
+    """NormalInverse.solve(y) against a dense solve with N = A^H A + lam^2 P^H P
+    assembled from A (brute force on 7 x 6 x 5), for several receiver counts,
+    lam = 0 (N = A^H A) and no receivers."""
+    g = Grid(7, 6, 5, 10.0, 1, 1600.0)
+    rng = _rng(11)
+    m = rng.uniform(1 / 3000.0 ** 2, 1 / 1600.0 ** 2, g.n)
+    A = oracle.helmholtz(g, m, 2 * np.pi * 11.0)
+    rec = np.sort(rng.choice(g.n, size=n_rec, replace=False))
+    P = oracle.restriction(g.n, rec)
+    Ad, Pd = A.toarray(), P.toarray()
+    N = Ad.conj().T @ Ad + lam ** 2 * Pd.conj().T @ Pd
+    Y = _crandn(rng, g.n, 3)
+    ref = np.linalg.solve(N, Y)
+    inv = oracle.NormalInverse(A, P, lam)
+    got = np.stack([inv.solve(Y[:, j]) for j in range(3)], axis=1)
+    assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+def test_objective_grad_same_by_both_normal_solvers(mode):
+    """The exact minimiser, J and g computed with a factor of N and with the
+    factors of A (Woodbury) agree to rounding on a two-frequency problem."""
+    p = wri_synth.custom_problem((11, 9, 8), nb=2, n_src=2, n_rec=7, seed=44, freqs=(6.0, 9.0))
+    a = oracle.objective_grad(p, mode=mode)
+    b = oracle.objective_grad(p, mode=mode, normal_solver="woodbury")
+    assert b["J"] == pytest.approx(a["J"], rel=1e-10)
+    for ua, ub in zip(a["u"], b["u"]):
+        assert np.linalg.norm(ua - ub) <= 1e-10 * np.linalg.norm(ua)
+    assert np.allclose(b["alpha"], a["alpha"], rtol=1e-10, atol=0)
+    ga, gb = a["g"][0].reshape(-1), b["g"][0].reshape(-1)
+    assert np.linalg.norm(ga - gb) <= 1e-9 * np.linalg.norm(ga)
