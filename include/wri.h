@@ -185,6 +185,31 @@ int wri_solve(const wri_grid* grids, int32_t n_grids, const float* const* m,
               int32_t flags, wri_c32* const* u_out, wri_result* res,
               void* ws, size_t ws_bytes, void* stream);
 
+/* Size of the fixed device scratch that wri_solve_noalloc uses as its workspace. */
+#define WRI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* wri_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, allocation-free serving loops, harnesses that forbid
+ * hipMalloc.  Arguments and results as in wri_solve, without ws / ws_bytes.
+ *   Workspace: a fixed scratch array of WRI_NOALLOC_SCRATCH_BYTES (64 MiB) in
+ *   the library's device code, one copy per device, held from the library's
+ *   first use on that device until the process ends.  The call allocates
+ *   nothing (no hipMalloc/hipFree, no graph, no events): the iterations are
+ *   launched eagerly on `stream` with the default slab tile (WRI_FLAG_NO_GRAPH
+ *   and WRI_FLAG_NO_AUTOTUNE are implied; the WRI_TILE environment variable
+ *   still forces a tile).
+ *   Limit: systems whose wri_workspace_bytes() exceeds the scratch are
+ *   rejected with WRI_ENOWS before any device work (e.g. up to about 8
+ *   systems of 64^3 cells fit).  WRI_FLAG_TIMING is rejected (WRI_EINVAL).
+ *   Sharing: every call on a device uses that device's one scratch and leaves
+ *   its contents behind (the solver initialises everything it reads).  Calls
+ *   that overlapped on one device would race on it; the library serialises
+ *   its solver calls within a process and returns only after the device work
+ *   of a call has finished. */
+int wri_solve_noalloc(const wri_grid* grids, int32_t n_grids, const float* const* m,
+                      const wri_system* sys, int32_t n_sys, int32_t mode, int32_t max_iter,
+                      int32_t flags, wri_c32* const* u_out, wri_result* res, void* stream);
+
 /* Objective and gradient in m (eqs. VarObj2, VarG2): runs the batched solve,
  * then writes
  *   J_out     HOST double, sum over systems of J_ij

@@ -974,6 +974,38 @@ int solve_common(const wri_grid* grids, int32_t n_grids, const float* const* m, 
   return ret;
 }
 
+// ---------------------------------------------------------------------------
+// fixed device scratch of the entry point that allocates nothing
+// ---------------------------------------------------------------------------
+
+// The workspace of wri_solve_noalloc: a file-scope device array, one copy per
+// device, held by the loaded code object until the process ends.  On the host
+// the name `scratch` is only a stand-in symbol: every kernel argument and copy
+// uses the per-device address that hipGetSymbolAddress returns.
+constexpr size_t kNoAllocBytes = WRI_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mutex;
+std::map<int, char*> g_scratch_addr;  // device -> address of its copy of `scratch`
+
+// Address of the current device's copy, looked up once per device (with that
+// device current) on its first call.
+int scratch_address(int dev, char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return WRI_OK;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr)
+    return fail(WRI_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+  g_scratch_addr[dev] = static_cast<char*>(ptr);
+  *out = static_cast<char*>(ptr);
+  return WRI_OK;
+}
+
 }  // namespace
 
 int report_error(int code, const char* fmt, ...) {
@@ -1008,6 +1040,33 @@ int wri_solve(const wri_grid* grids, int32_t n_grids, const float* const* m, con
               size_t ws_bytes, void* stream) {
   try {
     return solve_common(grids, n_grids, m, sys, n_sys, mode, max_iter, flags, u_out, res, ws, ws_bytes, stream,
+                        nullptr, nullptr, nullptr);
+  } catch (const std::exception& e) {
+    return fail(WRI_EINVAL, "exception: %s", e.what());
+  }
+}
+
+int wri_solve_noalloc(const wri_grid* grids, int32_t n_grids, const float* const* m, const wri_system* sys,
+                      int32_t n_sys, int32_t mode, int32_t max_iter, int32_t flags, wri_c32* const* u_out,
+                      wri_result* res, void* stream) {
+  try {
+    if (flags & WRI_FLAG_TIMING) return fail(WRI_EINVAL, "wri_solve_noalloc: WRI_FLAG_TIMING creates events");
+    int rc = validate(grids, n_grids, sys, n_sys, mode, max_iter);
+    if (rc != WRI_OK) return rc;
+    const size_t need = make_layout(grids, n_grids, sys, n_sys, flags).total;
+    if (need > kNoAllocBytes)
+      return fail(WRI_ENOWS,
+                  "wri_solve_noalloc: these systems need %zu bytes of workspace; the fixed scratch holds %zu "
+                  "(call wri_solve with a workspace of wri_workspace_bytes())", need, kNoAllocBytes);
+    int dev = 0;
+    WRI_HIP(hipGetDevice(&dev));
+    char* ws = nullptr;
+    rc = scratch_address(dev, &ws);
+    if (rc != WRI_OK) return rc;
+    // eager launches on the caller's stream (graph instantiation and the
+    // autotuner's events would allocate); the default tile unless WRI_TILE forces one
+    return solve_common(grids, n_grids, m, sys, n_sys, mode, max_iter,
+                        flags | WRI_FLAG_NO_GRAPH | WRI_FLAG_NO_AUTOTUNE, u_out, res, ws, kNoAllocBytes, stream,
                         nullptr, nullptr, nullptr);
   } catch (const std::exception& e) {
     return fail(WRI_EINVAL, "exception: %s", e.what());

@@ -124,6 +124,9 @@ def lib() -> ctypes.CDLL:
     L.wri_solve.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32, c_int32, c_int32,
                             c_int32, pp, POINTER(WriResult), vp, c_size_t, vp]
     L.wri_solve.restype = c_int
+    L.wri_solve_noalloc.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32, c_int32, c_int32,
+                                    c_int32, pp, POINTER(WriResult), vp]
+    L.wri_solve_noalloc.restype = c_int
     L.wri_objective_grad.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32, c_int32,
                                      c_int32, c_int32, POINTER(c_double), pp, pp, POINTER(WriResult), vp,
                                      c_size_t, vp]
@@ -185,7 +188,7 @@ def lib() -> ctypes.CDLL:
     return L
 
 
-EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_objective_grad", "estimate_source",
+EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_solve_noalloc", "wri_objective_grad", "estimate_source",
             "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version",
             "wri_tv_workspace_bytes", "wri_tv", "wri_lbfgs_workspace_bytes", "wri_lbfgs_direction",
             "wri_awri_workspace_bytes", "wri_awri", "wri_fwi_workspace_bytes", "wri_fwi_objective_grad",
@@ -321,6 +324,25 @@ def solve(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=None, return_u
     code = lib().wri_solve(batch.cgrids, len(batch.grids_py), batch.m_ptrs(), batch.csys, batch.nsys, mode,
                            int(max_iter), int(flags), _u_ptrs(batch, u_out), res, c_void_p(ws.data_ptr()),
                            ws.numel(), _stream(batch.device))
+    _check(code)
+    return u_out, _results(res, batch.nsys)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # WRI_NOALLOC_SCRATCH_BYTES
+
+
+def solve_noalloc(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=None):
+    """wri_solve_noalloc: the batched solve on the library's fixed device
+    scratch (no workspace, no device allocation inside the call).  u_out
+    (one tensor per system) is allocated here when not given.  Returns
+    (u list, results list)."""
+    mode = batch.mode if mode is None else mode
+    if u_out is None:
+        u_out = alloc_wavefields(batch)
+    res = (WriResult * max(1, batch.nsys))()
+    code = lib().wri_solve_noalloc(batch.cgrids, len(batch.grids_py), batch.m_ptrs(), batch.csys, batch.nsys,
+                                   mode, int(max_iter), int(flags), _u_ptrs(batch, u_out), res,
+                                   _stream(batch.device))
     _check(code)
     return u_out, _results(res, batch.nsys)
 

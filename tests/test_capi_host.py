@@ -314,3 +314,30 @@ def test_offgrid_entry_point_validates_before_device_work():
                                         None) == wri.EINVAL
     assert "position" in wri.last_error()
     assert ctypes.sizeof(wri.WriPositions) == 32
+
+
+def test_noalloc_rejects_systems_beyond_the_scratch_before_any_device_call():
+    """wri_solve_noalloc checks the workspace its systems need against the
+    fixed scratch (WRI_NOALLOC_SCRATCH_BYTES) before any device call, and
+    validates its arguments like wri_solve."""
+    txt = open(HEADER).read()
+    assert re.search(r"#define\s+WRI_NOALLOC_SCRATCH_BYTES\s+\(\(size_t\)64 << 20\)", txt)
+    assert wri.NOALLOC_SCRATCH_BYTES == 64 << 20
+    L = wri.lib()
+    rec = np.arange(4, dtype=np.int32)
+    g = (wri.WriGrid * 1)(wri.WriGrid(128, 128, 128, 10, 10.0, 1500.0))
+    s = (wri.WriSystem * 1)(wri.WriSystem(0, 5, 30.0, 0.1, 1e-4, wri.WriC64(1.0, 0.0), 4, 0,
+                                          rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          ctypes.c_void_p(0x1000)))
+    assert L.wri_workspace_bytes(g, 1, s, 1, wri.ESTIMATE, 0) > wri.NOALLOC_SCRATCH_BYTES
+    res = (wri.WriResult * 1)()
+    m = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x2000))
+    assert L.wri_solve_noalloc(g, 1, m, s, 1, wri.ESTIMATE, 10, 0, None, res, None) == wri.ENOWS
+    assert "scratch" in wri.last_error()
+    g2, s2, _ = _mk()
+    assert L.wri_solve_noalloc(g2, 1, m, s2, 1, wri.ESTIMATE, 10, wri.FLAG_TIMING, None, res, None) == wri.EINVAL
+    g3, s3, _ = _mk(dup=True)
+    assert L.wri_solve_noalloc(g3, 1, m, s3, 1, wri.ESTIMATE, 10, 0, None, res, None) == wri.EDUP
+    g4, s4, _ = _mk(src=720)
+    assert L.wri_solve_noalloc(g4, 1, m, s4, 1, wri.ESTIMATE, 10, 0, None, res, None) == wri.ERANGE
+
