@@ -97,19 +97,245 @@ def _cpu_worker(args):
     return out["iters"], out["seconds"], time.perf_counter() - t0
 
 
+# Cores this job may use on the GPU machine: the box allots 16 host cores per GPU
+# (more worker processes than that are killed), whatever os.cpu_count() says.
+HOST_CORE_SHARE = 16
+
+
+_THREAD_VARS = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+
+
+def _single_threaded_pool(procs):
+    """A spawn pool of `procs` workers that each run the oracle on one thread:
+    the thread-count variables are set before the workers import numpy (a
+    worker per core; the box exports OMP_NUM_THREADS = 16)."""
+    saved = {k: os.environ.get(k) for k in _THREAD_VARS}
+    for k in _THREAD_VARS:
+        os.environ[k] = "1"
+    try:
+        return mp.get_context("spawn").Pool(procs)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def host_description():
+    """CPU model, core counts and the library versions the CPU oracle runs on."""
+    import scipy
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity_cores": aff,
+            "core_share": HOST_CORE_SHARE, "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS", ""),
+            "numpy": np.__version__, "scipy": scipy.__version__}
+
+
 def cpu_baseline(name, systems, mean_iters, seconds, h):
-    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    procs = max(1, min(16, ncpu, len(systems)))
+    host = host_description()
+    procs = max(1, min(HOST_CORE_SHARE, host["affinity_cores"] or 1, len(systems)))
     scale = 42.0 ** 0.5 / h ** 2
-    with mp.get_context("spawn").Pool(procs) as pool:
+    with _single_threaded_pool(procs) as pool:
         outs = pool.map(_cpu_worker, [(name, k, seconds, scale) for k in systems[:procs]])
     it_per_s = sum(it / max(sec, 1e-9) for it, sec, _ in outs)
     solves_per_s = it_per_s / mean_iters
     return {"value": solves_per_s, "unit": "solves/s", "cores": procs, "kind": "oracle",
             "sample": (f"oracle complex128 CGLS (scipy CSR mat-vecs) on {procs} of the {name} systems, one "
-                       f"process per core, {seconds:.0f} s each ({sum(o[0] for o in outs)} iterations total, "
-                       f"{it_per_s:.2f} it/s aggregate); solves/s = it/s / {mean_iters:.0f} (mean GPU "
-                       f"iterations per solve at rtol 1e-4)")}
+                       f"single-threaded process per core (the box's share of {HOST_CORE_SHARE} cores), "
+                       f"{seconds:.0f} s each "
+                       f"({sum(o[0] for o in outs)} iterations total, {it_per_s:.2f} it/s aggregate); "
+                       f"solves/s = it/s / {mean_iters:.0f} (mean GPU iterations per solve at rtol 1e-4); "
+                       f"completed CPU solves and the direct oracle: profiles/cpu_oracle_host_baseline.md"),
+            "host": host,
+            "direct_oracle_16cube_s": _direct_oracle_seconds("tiny")}
+
+
+def _cpu_complete_worker(args):
+    """One job of the CPU validation run: ("cgls", config, system) runs the
+    oracle's complex128 CGLS to the system's rtol; ("direct", config, system,
+    solver) the oracle's exact solve (objective and gradient) of one system."""
+    import oracle
+    import wri_synth
+    kind, name, k = args[:3]
+    if kind == "direct":
+        p = wri_synth.make_config(name, seed=0, data="none" if name == "tiny" else "green")
+        if name == "tiny":
+            p = p.with_data(oracle.observed_data(p, seed=0))
+        p = p.subset([k])
+        t0 = time.perf_counter()
+        oracle.objective_grad(p, return_fields=False, normal_solver=args[3])
+        return {"kind": "direct", "config": name, "system": k, "solver": args[3], "cells": p.grids[0].n,
+                "seconds": time.perf_counter() - t0}
+    p = wri_synth.make_config(name, seed=0)
+    s = p.systems[k]
+    A, P, e = oracle.system_operators(p, k)
+    t0 = time.perf_counter()
+    out = oracle.cgls(A, P, s.lam, s.src, "estimate", 0, s.d, rtol=s.rtol, maxiter=10 ** 9,
+                      alpha_scale=42.0 ** 0.5 / p.grids[s.grid].h ** 2)
+    return {"kind": "cgls", "config": name, "system": k, "cells": p.grids[s.grid].n, "iters": out["iters"],
+            "seconds": time.perf_counter() - t0, "rtol": s.rtol}
+
+
+def cpu_validate(dev, big):
+    """The CPU oracle on the host of the GPU machine, run to completion: complex128
+    CGLS on every system of the medium workload (and on `big` systems of the
+    128^3 workload), one process per job within the box's core share, next to
+    the direct oracle (sparse LU) at 16^3 and 32^3; the GPU's iteration counts
+    for the same systems (batched, complex64 with float64 reductions) for the
+    it/s -> solves/s conversion of the default run's CPU baseline."""
+    import torch
+    import wri_synth
+    from paper_2410_18429_amd import wri
+    host = host_description()
+    jobs = [("direct", "tiny", 0, "factor_N"), ("direct", "crop32", 0, "factor_N"),
+            ("direct", "crop32", 0, "woodbury")]
+    jobs += [("cgls", "medium", k) for k in range(8)]
+    jobs += [("cgls", "differentiation", k) for k in (0, 23, 47)[:big]]
+    t0 = time.perf_counter()
+    outs = []
+    with _single_threaded_pool(min(HOST_CORE_SHARE, len(jobs))) as pool:
+        for o in pool.imap_unordered(_cpu_complete_worker, jobs):
+            outs.append(o)
+            print(f"[cpu-validate] {json.dumps(o)}", file=sys.stderr, flush=True)
+    outs.sort(key=lambda o: (o["kind"], o["config"], o["system"], o.get("solver", "")))
+    wall = time.perf_counter() - t0
+    gpu = {}
+    for name in sorted(set(o["config"] for o in outs if o["kind"] == "cgls")):
+        ks = [o["system"] for o in outs if o["kind"] == "cgls" and o["config"] == name]
+        prob = wri_synth.make_config(name, seed=0)
+        b = wri.Batch(prob.subset(ks), device=dev)
+        _, _, res = wri.objective_grad(b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, res = wri.objective_grad(b)
+        torch.cuda.synchronize()
+        gpu[name] = {"systems": ks, "iters": [r["iters"] for r in res], "seconds": time.perf_counter() - t1}
+    for o in outs:
+        if o["kind"] == "cgls":
+            g = gpu[o["config"]]
+            o["gpu_iters"] = g["iters"][g["systems"].index(o["system"])]
+    med = [o for o in outs if o["kind"] == "cgls" and o["config"] == "medium"]
+    line = {"mode": "cpu_validate", "host": host, "pool_wall_s": round(wall, 1), "jobs": outs, "gpu": gpu,
+            "medium_cpu_solves_per_s_all_jobs_parallel": len(med) / max(o["seconds"] for o in med),
+            "medium_cpu_seconds_per_solve_mean": float(np.mean([o["seconds"] for o in med])),
+            "medium_cpu_over_gpu_iters": float(np.mean([o["iters"] / o["gpu_iters"] for o in med]))}
+    print(json.dumps(line), flush=True)
+
+
+def _direct_oracle_seconds(name):
+    """Wall time of the oracle's exact solve (SuperLU factor of the normal
+    matrix, objective and gradient) of the first system of a small workload."""
+    import oracle
+    import wri_synth
+    p = wri_synth.make_config(name, seed=0, data="none")
+    p = p.with_data(oracle.observed_data(p, seed=0)).subset([0])
+    t0 = time.perf_counter()
+    oracle.objective_grad(p, return_fields=False)
+    return round(time.perf_counter() - t0, 3)
+
+
+def error_vs_fp64(prob, batch, dev, sample=(0, 23, 47)):
+    """Errors of the GPU results against float64, computed by the oracle on
+    the host after the timed region (one more GPU evaluation provides the
+    wavefields):
+      * true normal residual ||S^H (b - S x)|| / ||S^H b|| in float64 of the
+        returned (u, alpha) of sampled systems (the solver stops on the
+        recurred value at rtol 1e-4);
+      * J of those systems recomputed in float64 from (u, alpha) against the
+        GPU's recurred J;
+      * alpha_ls = (A u)[src] in float64 against the GPU's;
+      * the 32^3 crop of the same model (48 systems, rtol 1e-8) against the
+        exact float64 minimiser of the golden file: wavefield-free J, alpha and
+        gradient errors."""
+    import torch
+    import oracle
+    import wri_synth
+    from paper_2410_18429_amd import wri
+    u = wri.alloc_wavefields(batch)
+    J, grads, res = wri.objective_grad(batch, u_out=u)
+    torch.cuda.synchronize()
+    per = []
+    ops = {}
+    for k in sample:
+        s = prob.systems[k]
+        if s.freq not in ops:
+            ops[s.freq] = oracle.system_operators(prob, k)[:2]
+        A, P = ops[s.freq]
+        e = oracle.unit_vector(A.shape[0], s.src)
+        uk = u[k].cpu().numpy().astype(np.complex128)
+        t1, t2 = oracle.objective_terms(A, P, s.lam, uk, res[k]["alpha"], e, s.d)
+        tr = oracle.normal_residual(A, P, s.lam, s.src, "estimate", 0, s.d, uk, res[k]["alpha"])
+        a64 = (A @ uk)[s.src]
+        per.append({"system": k, "true_normal_residual": float(tr), "recurred_relres": res[k]["relres"],
+                    "J_rel_err": abs(res[k]["J"] - (t1 + t2)) / (t1 + t2),
+                    "alpha_ls_rel_err": abs(res[k]["alpha_ls"] - a64) / abs(a64)})
+    del u
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "crop32_oracle.npz"))
+    cp = wri_synth.make_config("crop32", seed=0)
+    cb = wri.Batch(cp, device=dev)
+    Jc, gc, rc = wri.objective_grad(cb)
+    torch.cuda.synchronize()
+    g = gc[0].cpu().numpy().astype(np.float64)
+    gref = gold["g"].reshape(-1)
+    alpha = np.array([r["alpha_ls"] for r in rc])
+    crop = {"J_rel_err": abs(Jc - float(gold["J"])) / float(gold["J"]),
+            "alpha_max_rel_err": float(np.max(np.abs(alpha - gold["alpha"]) / np.abs(gold["alpha"]))),
+            "grad_rel_err": float(np.linalg.norm(g - gref) / np.linalg.norm(gref)),
+            "systems": len(cp.systems), "rtol": 1e-8}
+    return {"reference": "float64 oracle (host)", "sampled_128cube": per, "crop32_vs_exact_minimiser": crop}
+
+
+def tail_probe(dev, tiles, k1=600, k2=800):
+    """Steady-state kernel time per CGLS iteration (forward + adjoint, HIP events
+    around every launch) against the number of systems still iterating, per
+    tile: batches of n systems of the 128^3 workload (spread over its three
+    frequencies) and of the large workload's 256 x 256 x 192 grid, rtol 0, timed
+    over iterations k1..k2 as the difference of a run to k1 and one to k2
+    iterations, after the wavefield has filled the grid (the first few hundred
+    iterations of a solve run faster: the fields are still mostly zero)."""
+    import torch
+    import wri_synth
+    from paper_2410_18429_amd import wri
+    out = []
+    for name, counts in (("differentiation", (1, 2, 3, 4, 6, 8, 12, 16, 48)), ("large", (1, 2, 3, 4, 6, 8))):
+        prob = wri_synth.make_config(name, seed=0)
+        nsys = len(prob.systems)
+        for tile in tiles:
+            os.environ["WRI_TILE"] = tile
+            for n in counts:
+                pick = [int(round(i * nsys / n)) for i in range(n)]
+                q = prob.subset(pick).with_rtol(0.0)
+                b = wri.Batch(q, device=dev)
+                t = {}
+                for K in (k1, k2):
+                    wri.objective_grad(b, max_iter=K, flags=wri.FLAG_TIMING)
+                    torch.cuda.synchronize()
+                    kt = wri.kernel_times()
+                    t[K] = (kt["fwd_ms"] + kt["adj_ms"], kt["fwd_bytes"] + kt["adj_bytes"])
+                ms = (t[k2][0] - t[k1][0]) / (k2 - k1)
+                gbs = (t[k2][1] - t[k1][1]) / ((t[k2][0] - t[k1][0]) * 1e-3) / 1e9
+                rec = {"workload": name, "tile": tile, "systems": n, "cells": n * q.grids[0].n,
+                       "ms_per_iteration": round(ms, 4), "gbs": round(gbs, 1)}
+                print(json.dumps(rec), file=sys.stderr, flush=True)
+                out.append(rec)
+                del b
+        os.environ.pop("WRI_TILE", None)
+    return out
+
+
+def stream_ceilings(wri, dev, n=1 << 27, reps=5):
+    """GB/s of the library's streaming probe for each access mix (copy, forward,
+    forward with the x update, adjoint) over n complex64 elements per array."""
+    return {mix: wri.stream_probe(mix, n, reps, device=dev) for mix in ("copy", "fwd", "fwd_x", "adj")}
 
 
 def awri_bench(name, updates, dev):
@@ -469,6 +695,14 @@ def main():
     ap.add_argument("--fwi", action="store_true",
                     help="reduced-FWI baseline measurement instead of the headline: objective-and-gradient "
                          "evaluations of FWI and WRI on --config")
+    ap.add_argument("--cpu-validate", type=int, default=-1,
+                    help="CPU oracle run to completion on the medium workload's systems (and this many 128^3 "
+                         "systems), the direct oracle at 16^3 and 32^3, GPU iteration counts alongside")
+    ap.add_argument("--tail-probe", default="",
+                    help="steady-state time per iteration against the number of systems still iterating, for "
+                         "these tiles (';'-separated, e.g. '4,4,32,2,4;4,4,32,1,4')")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only the streaming probe of every access mix (profiling run), one JSON line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="counter calibration: copy a buffer of this many MiB three times and exit")
     args = ap.parse_args()
@@ -490,6 +724,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return
+    if args.tail_probe:
+        print(json.dumps({"tail_probe": tail_probe(dev, args.tail_probe.split(";"))}), flush=True)
+        return
+    if args.stream_probe:
+        print(json.dumps({"stream_ceiling_gbs": stream_ceilings(wri, dev)}), flush=True)
+        return
+    if args.cpu_validate >= 0:
+        cpu_validate(dev, args.cpu_validate)
         return
     if args.awri:
         awri_bench("medium" if args.config == "differentiation" else args.config, args.awri_updates, dev)
@@ -586,6 +829,28 @@ def main():
                 "fwd_gbs_full_batch": round(fwd_full_gbs, 1), "adj_gbs_full_batch": round(adj_full_gbs, 1),
                 "bytes_per_cell": bytes_note(kt["tile_pf"]), "tile": tile}
 
+    # practical streaming ceilings on this device: a plain grid-stride kernel with
+    # the access mix of each fused launch and none of its arithmetic
+    # (wri_stream_probe, 2^27 complex64 elements per array, best of five launches per variant)
+    ceil = stream_ceilings(wri, dev)
+    pf = kt["tile_pf"]
+    if dominant == "fwd":
+        # forward launches alternate between the plain and the x-updating mix
+        b0, b1 = (28.0, 52.0) if pf >= 2 else (36.0, 60.0)
+        mix_ceiling = (b0 + b1) / (b0 / ceil["fwd"] + b1 / ceil["fwd_x"])
+        if pf < 2:
+            mix_ceiling = None   # the probe has no mix with a stored t
+    else:
+        mix_ceiling = ceil["adj"]
+    roofline["stream_ceiling_gbs"] = {k: round(v, 1) for k, v in ceil.items()}
+    roofline["copy_ceiling_gbs"] = round(ceil["copy"], 1)
+    roofline["frac_of_copy_ceiling"] = round(ach / ceil["copy"], 4)
+    roofline["mix_ceiling_gbs"] = round(mix_ceiling, 1) if mix_ceiling else None
+    roofline["frac_of_mix_ceiling"] = round(ach / mix_ceiling, 4) if mix_ceiling else None
+    roofline["adj_frac_of_mix_ceiling_full_batch"] = round(adj_full_gbs / ceil["adj"], 4)
+    log(f"[bench] stream ceilings {json.dumps(roofline['stream_ceiling_gbs'])}; dominant kernel at "
+        f"{ach / ceil['copy']:.3f} of the copy, {roofline['frac_of_mix_ceiling']} of its own mix")
+
     plain = None
     if not args.no_plain and args.plain_sample > 0:
         freqs = sorted(set(s.freq for s in prob.systems))
@@ -612,11 +877,16 @@ def main():
             f"{plain['same_systems_batched']:.3f}")
 
     cpu = None
+    errors = None
     if not args.no_cpu:
         log("[bench] cpu baseline ...")
         cpu = cpu_baseline(args.config, list(range(0, nsys, max(1, nsys // 16))), float(iters.mean()),
                            args.cpu_seconds, g.h)
         log(f"[bench] cpu: {cpu['value']:.5f} solves/s on {cpu['cores']} cores")
+        if args.config == "differentiation":
+            log("[bench] error against float64 ...")
+            errors = error_vs_fp64(prob, batch, dev)
+            log(f"[bench] errors: {json.dumps(errors)}")
 
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1,
@@ -631,6 +901,7 @@ def main():
                    "status": statuses, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "error_vs_fp64": errors,
         "plain": plain,
         "batched_vs_plain": round(value / plain["value"], 3) if plain else None,
     }

@@ -463,6 +463,28 @@ typedef struct {
 /* Fills *out; WRI_EINVAL if no timed call has completed on this thread. */
 int wri_kernel_times(wri_timing* out);
 
+/* Streaming bandwidth probe (a measurement helper, not a step of the method):
+ * one grid-stride kernel with the HBM access mix of a fused CGLS launch and
+ * none of its arithmetic, the practical bandwidth ceiling that the fused
+ * kernels' fraction of the 8 TB/s peak is set against.  Per complex64
+ * element:
+ *   mix 0  copy: read a, write c                                    16 B
+ *   mix 1  forward pass: read s, p, m; write p (no x update)         28 B
+ *   mix 2  forward pass with the x update: + read x, p'; write x     52 B
+ *   mix 3  adjoint pass: read r, p, m; write r, s                    36 B
+ *   n        elements per array (even, > 0)
+ *   reps     timed launches after one warm-up launch
+ *   ws       DEVICE workspace of ws_bytes >= wri_stream_probe_bytes(mix, n);
+ *            its contents are read and overwritten (values are arbitrary)
+ *   gbs_out  HOST: bytes of the mix / the shortest launch time (HIP events on
+ *            `stream`), in GB/s, the best over the probe's variants (one or
+ *            four element pairs in flight per thread; ordinary or
+ *            non-temporal stores)
+ * Returns WRI_EINVAL / WRI_ENOWS for bad arguments, WRI_EHIP on a HIP error. */
+size_t wri_stream_probe_bytes(int32_t mix, int64_t n);
+int wri_stream_probe(int32_t mix, int64_t n, int32_t reps, void* ws, size_t ws_bytes, void* stream,
+                     double* gbs_out);
+
 /* Text of a return code; message of the last error on this thread. */
 const char* wri_strerror(int code);
 const char* wri_last_error(void);

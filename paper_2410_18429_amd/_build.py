@@ -11,7 +11,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwri.so")
-SOURCES = ["kernels.hip", "capi.hip", "outer.hip", "fwi.hip", "resample.hip", "offgrid.hip"]
+SOURCES = ["kernels.hip", "capi.hip", "outer.hip", "fwi.hip", "resample.hip", "offgrid.hip", "probe.hip"]
 ARCH = os.environ.get("WRI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -25,11 +25,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# Host-sanitized variant for the CPU tests of the C ABI's host code
+# (validation, planner, workspace layout, receiver column maps): AddressSanitizer
+# and UndefinedBehaviorSanitizer on the host compilation only, device code as in
+# the product build.  Loaded with the ASan runtime preloaded
+# (tests/test_capi_host.py drives it in a subprocess).
+LIB_HOSTSAN = os.path.join(PKG, "libwri_hostsan.so")
+HOSTSAN_FLAGS = [
+    "-Xarch_host", "-fsanitize=address",
+    "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=undefined",
+    "-Xarch_host", "-fno-omit-frame-pointer",
+    "-Xarch_host", "-g",
+]
+
+
+def build(verbose: bool = False, host_sanitized: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, *srcs, "-o", tmp]
+    out_lib = LIB_HOSTSAN if host_sanitized else LIB
+    tmp = out_lib + ".tmp"
+    cmd = [hipcc, *FLAGS, *(HOSTSAN_FLAGS if host_sanitized else []), *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
@@ -39,9 +55,9 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({proc.returncode}):\n{out}")
     if verbose and out:
         print(out)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out_lib)
+    return out_lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, host_sanitized="--host-sanitized" in sys.argv))

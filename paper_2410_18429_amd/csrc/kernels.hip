@@ -871,6 +871,11 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   const int plane = C.plane;
   const double bf = beta;
   const double w2 = S.omega_d * S.omega_d;
+  // the table's scalars that the march uses, read once (the receiver-row
+  // stores could alias the table, so reads through S would be repeated)
+  const double sp_scale = S.sp_scale_d, h2inv = S.h2inv_d, om = S.omega_d, inv_nb = S.inv_nb_d;
+  const double lam = S.lam_d, acol = S.alpha_c;
+  const int nz = S.nz, nbw = S.nb;
   int coff[RY];
 #pragma unroll
   for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
@@ -1039,7 +1044,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
     for (int j = 0; j < RY; ++j) mn[j] = bld1(Rm, own_b(z + 1, j, 4));
     const bool zin = z < C.z1;
     const unsigned zbit = zin ? 0u : kOOB;
-    const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
+    const double sz2 = sponge_axis_d(z, nz, nbw, inv_nb);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       const int ly = w * RY + j;
@@ -1047,11 +1052,11 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       const float2 xp = pl[cur][ly + 1][lane + 2];
       const float2 ym = (j > 0) ? pc[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
       const float2 yp = (j < RY - 1) ? pc[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
-      const double b = S.sp_scale_d * (sxy2[j] + sz2);
-      double2 td = helm(pc[j], xm, xp, ym, yp, pm[j], pnx[j], S.h2inv_d, w2 * (double)mz[j], -(S.omega_d * b));
+      const double b = sp_scale * (sxy2[j] + sz2);
+      double2 td = helm(pc[j], xm, xp, ym, yp, pm[j], pnx[j], h2inv, w2 * (double)mz[j], -(om * b));
       if (j == srcj && z == sz) {
-        td.x -= S.alpha_c * pa_new.x;
-        td.y -= S.alpha_c * pa_new.y;
+        td.x -= acol * pa_new.x;
+        td.y -= acol * pa_new.y;
       }
       const float2 tv = round2(td);
       const bool live = C.in[j] && zin;
@@ -1061,7 +1066,7 @@ k_fwd_pf(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       acc += live ? norm2d(tv) : 0.0;
       if (rc.at(j, z - C.z0)) {  // receiver row of S p: lambda p at the receiver cell
         const int q = rc.take(S, j);
-        const float2 tq = f2((float)(S.lam_d * pc[j].x), (float)(S.lam_d * pc[j].y));
+        const float2 tq = f2((float)(lam * pc[j].x), (float)(lam * pc[j].y));
         st2(t2v, q, tq);
         acc += norm2d(tq);
       }
@@ -1420,6 +1425,12 @@ k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   const int plane = C.plane;
   const double af = a;
   const double w2 = S.omega_d * S.omega_d;
+  // the table's scalars that the march uses, read once: the receiver-row
+  // stores go through a global pointer that could alias the table, so reads
+  // through S inside the loop would be repeated after every store
+  const double sp_scale = S.sp_scale_d, h2inv = S.h2inv_d, om = S.omega_d, inv_nb = S.inv_nb_d;
+  const double lam = S.lam_d, acol = S.alpha_c;
+  const int nz = S.nz, nbw = S.nb;
   int coff[RY];
 #pragma unroll
   for (int j = 0; j < RY; ++j) coff[j] = C.gy[j] * S.nx + C.gx;
@@ -1538,8 +1549,8 @@ k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   // into LDS buffer br (br < 0: own rows only) from raw set st; commit p_k of
   // plane zz+1 to LDS buffer bp ^ 1 and move the p registers up one plane.
   auto tphase = [&](const int st, int zz, int bp, int br) __attribute__((always_inline)) {
-    const bool zok = zz >= 0 && zz < S.nz;
-    const double sz2 = sponge_axis_d(zz, S.nz, S.nb, S.inv_nb_d);
+    const bool zok = zz >= 0 && zz < nz;
+    const double sz2 = sponge_axis_d(zz, nz, nbw, inv_nb);
     const bool zsrc = zz == sz;
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
@@ -1548,12 +1559,12 @@ k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       const float2 xp = pp[bp][ly][lane + 3];
       const float2 ym = (j > 0) ? pzc[j > 0 ? j - 1 : 0] : pp[bp][ly - 1][lane + 2];
       const float2 yp = (j < RY - 1) ? pzc[j < RY - 1 ? j + 1 : 0] : pp[bp][ly + 1][lane + 2];
-      const double b = S.sp_scale_d * (sxy2[j] + sz2);
-      double2 td = helm(pzc[j], xm, xp, ym, yp, pzm[j], rp[st][j], S.h2inv_d, w2 * (double)rmr[st][j],
-                         -(S.omega_d * b));
+      const double b = sp_scale * (sxy2[j] + sz2);
+      double2 td = helm(pzc[j], xm, xp, ym, yp, pzm[j], rp[st][j], h2inv, w2 * (double)rmr[st][j],
+                         -(om * b));
       if (j == srcj && zsrc) {
-        td.x -= S.alpha_c * pa.x;
-        td.y -= S.alpha_c * pa.y;
+        td.x -= acol * pa.x;
+        td.y -= acol * pa.y;
       }
       const double ae = (zok && C.in[j]) ? af : 0.0;
       rnew[j] = setup ? rr[st][j] : axpy2(rr[st][j], -ae, round2(td));
@@ -1568,12 +1579,12 @@ k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
         const float2 xp = pp[bp][cy][cx + 1];
         const float2 ym = pp[bp][cy - 1][cx];
         const float2 yp = pp[bp][cy + 1][cx];
-        const double b = S.sp_scale_d * (hsxy[q] + sz2);
-        double2 td = helm(hpc[q], xm, xp, ym, yp, hpm[q], hp[st][q], S.h2inv_d, w2 * (double)hmr[st][q],
-                           -(S.omega_d * b));
+        const double b = sp_scale * (hsxy[q] + sz2);
+        double2 td = helm(hpc[q], xm, xp, ym, yp, hpm[q], hp[st][q], h2inv, w2 * (double)hmr[st][q],
+                           -(om * b));
         if (hsrc[q] && zsrc) {
-          td.x -= S.alpha_c * pa.x;
-          td.y -= S.alpha_c * pa.y;
+          td.x -= acol * pa.x;
+          td.y -= acol * pa.y;
         }
         const double ae = (zok && hin[q]) ? af : 0.0;
         const float2 rv = setup ? hr[st][q] : axpy2(hr[st][q], -ae, round2(td));
@@ -1650,7 +1661,7 @@ k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
   auto step = [&](const int st, int z) __attribute__((always_inline)) {
     const bool zin = z < C.z1;
     const unsigned zbit = zin ? 0u : kOOB;
-    const double sz2 = sponge_axis_d(z, S.nz, S.nb, S.inv_nb_d);
+    const double sz2 = sponge_axis_d(z, nz, nbw, inv_nb);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       const int ly = w * RY + j;
@@ -1658,8 +1669,8 @@ k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
       const float2 xp = pl[cur][ly + 1][lane + 2];
       const float2 ym = (j > 0) ? rc_[j > 0 ? j - 1 : 0] : pl[cur][ly][lane + 1];
       const float2 yp = (j < RY - 1) ? rc_[j < RY - 1 ? j + 1 : 0] : pl[cur][ly + 2][lane + 1];
-      const double b = S.sp_scale_d * (sxy2[j] + sz2);
-      double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], S.h2inv_d, w2 * (double)mq0[j], S.omega_d * b);
+      const double b = sp_scale * (sxy2[j] + sz2);
+      double2 sd = helm(rc_[j], xm, xp, ym, yp, rm[j], rnx[j], h2inv, w2 * (double)mq0[j], om * b);
       if (rc.at(j, z - C.z0)) {  // receiver column of S^H: lambda r2 at the receiver cell
         const int q = rc.take(S, j);
         float2 r2 = ld2(r2v, q);
@@ -1667,12 +1678,12 @@ k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
           r2 = axpy2(r2, -af, ld2(t2v, q));
           st2(r2v, q, r2);
         }
-        sd.x += S.lam_d * r2.x;
-        sd.y += S.lam_d * r2.y;
+        sd.x += lam * r2.x;
+        sd.y += lam * r2.y;
       }
       const float2 s = round2(sd);
       if (j == srcj && src_in_slab && z == sz) {
-        sa = make_double2(-S.alpha_c * (double)rc_[j].x, -S.alpha_c * (double)rc_[j].y);
+        sa = make_double2(-acol * (double)rc_[j].x, -acol * (double)rc_[j].y);
         acc += sa.x * sa.x + sa.y * sa.y;
       }
       const bool live = C.in[j] && zin;

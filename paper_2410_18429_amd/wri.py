@@ -17,7 +17,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libwri.so")
+# WRI_LIBRARY selects another build of the same library (the host-sanitized
+# one of the CPU tests); the default is the in-tree libwri.so.
+LIB_PATH = os.environ.get("WRI_LIBRARY") or os.path.join(_HERE, "libwri.so")
 
 KNOWN = 0
 ESTIMATE = 1
@@ -144,6 +146,10 @@ def lib() -> ctypes.CDLL:
     L.wri_version.restype = c_int
     L.wri_kernel_times.argtypes = [POINTER(WriTiming)]
     L.wri_kernel_times.restype = c_int
+    L.wri_stream_probe_bytes.argtypes = [c_int32, ctypes.c_int64]
+    L.wri_stream_probe_bytes.restype = c_size_t
+    L.wri_stream_probe.argtypes = [c_int32, ctypes.c_int64, c_int32, vp, c_size_t, vp, POINTER(c_double)]
+    L.wri_stream_probe.restype = c_int
     L.wri_tv_workspace_bytes.argtypes = [POINTER(WriGrid)]
     L.wri_tv_workspace_bytes.restype = c_size_t
     L.wri_tv.argtypes = [POINTER(WriGrid), vp, c_double, c_double, POINTER(c_double), vp, vp, c_size_t, vp]
@@ -188,7 +194,8 @@ def lib() -> ctypes.CDLL:
     return L
 
 
-EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_solve_noalloc", "wri_objective_grad", "estimate_source",
+EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_solve_noalloc", "wri_stream_probe_bytes",
+            "wri_stream_probe", "wri_objective_grad", "estimate_source",
             "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version",
             "wri_tv_workspace_bytes", "wri_tv", "wri_lbfgs_workspace_bytes", "wri_lbfgs_direction",
             "wri_awri_workspace_bytes", "wri_awri", "wri_fwi_workspace_bytes", "wri_fwi_objective_grad",
@@ -201,6 +208,24 @@ def kernel_times() -> dict:
     t = WriTiming()
     _check(lib().wri_kernel_times(ctypes.byref(t)))
     return {name: getattr(t, name) for name, _ in WriTiming._fields_}
+
+
+STREAM_MIXES = {"copy": 0, "fwd": 1, "fwd_x": 2, "adj": 3}
+
+
+def stream_probe(mix: str, n: int, reps: int = 5, device="cuda") -> float:
+    """wri_stream_probe: GB/s of a plain streaming kernel with the access mix
+    of a fused launch (see STREAM_MIXES) over n complex64 elements per array."""
+    code = STREAM_MIXES[mix]
+    nbytes = lib().wri_stream_probe_bytes(code, int(n))
+    if nbytes == 0:
+        raise WriError(EINVAL, "bad stream probe size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    out = c_double(0.0)
+    _check(lib().wri_stream_probe(code, int(n), int(reps), c_void_p(ws.data_ptr()), nbytes,
+                                  _stream(torch.device(device)), ctypes.byref(out)))
+    del ws
+    return out.value
 
 
 def last_error() -> str:

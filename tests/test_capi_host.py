@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 import tempfile
 
 import numpy as np
@@ -341,3 +342,26 @@ def test_noalloc_rejects_systems_beyond_the_scratch_before_any_device_call():
     g4, s4, _ = _mk(src=720)
     assert L.wri_solve_noalloc(g4, 1, m, s4, 1, wri.ESTIMATE, 10, 0, None, res, None) == wri.ERANGE
 
+
+def test_host_code_under_address_and_undefined_behaviour_sanitizers():
+    """The host-only cases of this file again, in a subprocess against the
+    library built with AddressSanitizer and UndefinedBehaviorSanitizer on its
+    host code (`python -m paper_2410_18429_amd._build --host-sanitized`, also
+    done by the package build), the ASan runtime preloaded: an out-of-bounds
+    access, a use after free or undefined behaviour in argument validation,
+    the planner, the workspace layout or the receiver maps aborts the run."""
+    san = os.path.join(ROOT, "paper_2410_18429_amd", "libwri_hostsan.so")
+    if not os.path.exists(san):
+        pytest.skip("host-sanitized library not built")
+    syms = subprocess.check_output(["nm", "-D", san]).decode()
+    assert "__asan_report" in syms and "__ubsan_handle" in syms
+    rt = subprocess.check_output(["/opt/rocm/llvm/bin/clang", "-print-file-name=libclang_rt.asan-x86_64.so"])
+    rt = rt.decode().strip()
+    assert os.path.exists(rt), rt
+    env = dict(os.environ, LD_PRELOAD=rt, WRI_LIBRARY=san,
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    proc = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider", __file__,
+                           "-k", "not sanitizers"], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    tail = (proc.stdout + proc.stderr)[-3000:]
+    assert proc.returncode == 0, tail
+    assert "passed" in proc.stdout and "ERROR: AddressSanitizer" not in tail and "runtime error" not in tail
