@@ -332,6 +332,63 @@ def tail_probe(dev, tiles, k1=600, k2=800):
     return out
 
 
+def precond_bench(dev, steps, rtols=(1e-4, 1e-5), ref_rtol=1e-8, sample=(0, 16, 32, 47)):
+    """The 128^3 workload (48 systems) solved by the plain batched CGLS (the
+    headline method) and by the V-cycle-preconditioned CGLS (row f4): seconds
+    per objective-and-gradient evaluation, iteration counts, and the wavefield
+    and source-weight errors of both against a tight preconditioned solve
+    (rtol 1e-8) of the same systems, on sampled systems."""
+    import torch
+    import wri_synth
+    from paper_2410_18429_amd import wri
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    prob = wri_synth.make_config("differentiation", seed=0)
+    nsys = len(prob.systems)
+    b = wri.Batch(prob, device=dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, out
+
+    def fields(fn):
+        u = wri.alloc_wavefields(b)
+        _, _, res = fn(u)
+        torch.cuda.synchronize()
+        return [u[k].cpu().numpy().astype(np.complex128) for k in sample], [res[k]["alpha_ls"] for k in sample], res
+
+    b.set_rtol(ref_rtol)
+    ref_u, ref_a, ref_res = fields(lambda u: wri.objective_grad_precond(b, u_out=u, max_iter=100000))
+    log(f"[precond] reference: rtol {ref_rtol:g}, iterations {[ref_res[k]['iters'] for k in sample]}")
+
+    def errs(us, als):
+        return ([float(np.linalg.norm(u - r) / np.linalg.norm(r)) for u, r in zip(us, ref_u)],
+                [float(abs(a - r) / abs(r)) for a, r in zip(als, ref_a)])
+
+    out = {"mode": "precond", "workload": "differentiation: 128x128x128 h=10 m, 48 systems, ESTIMATE",
+           "systems": nsys, "steps": steps, "reference_rtol": ref_rtol, "sample": list(sample),
+           "reference_iters": [ref_res[k]["iters"] for k in sample], "runs": []}
+    for rt in rtols:
+        b.set_rtol(rt)
+        for name, call in (("plain", lambda u=None: wri.objective_grad(b, u_out=u)),
+                           ("precond", lambda u=None: wri.objective_grad_precond(b, u_out=u))):
+            sec, (_, _, res) = timed(call)
+            us, als, _ = fields(lambda u: call(u))
+            eu, ea = errs(us, als)
+            it = np.array([r["iters"] for r in res])
+            rec = {"solver": name, "rtol": rt, "seconds_per_evaluation": round(sec, 4),
+                   "solves_per_s": round(nsys / sec, 3), "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+                   "status": sorted(set(r["status"] for r in res)),
+                   "u_rel_err_vs_reference": eu, "alpha_rel_err_vs_reference": ea}
+            log(f"[precond] {json.dumps(rec)}")
+            out["runs"].append(rec)
+    print(json.dumps(out), flush=True)
+
+
 def stream_ceilings(wri, dev, n=1 << 27, reps=5):
     """GB/s of the library's streaming probe for each access mix (copy, forward,
     forward with the x update, adjoint) over n complex64 elements per array."""
@@ -701,6 +758,9 @@ def main():
     ap.add_argument("--tail-probe", default="",
                     help="steady-state time per iteration against the number of systems still iterating, for "
                          "these tiles (';'-separated, e.g. '4,4,32,2,4;4,4,32,1,4')")
+    ap.add_argument("--precond", action="store_true",
+                    help="the V-cycle-preconditioned solver against the plain one on the 128^3 workload "
+                         "(time per evaluation, iterations, errors against a tight solve), one JSON line")
     ap.add_argument("--stream-probe", action="store_true",
                     help="only the streaming probe of every access mix (profiling run), one JSON line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -727,6 +787,9 @@ def main():
         return
     if args.tail_probe:
         print(json.dumps({"tail_probe": tail_probe(dev, args.tail_probe.split(";"))}), flush=True)
+        return
+    if args.precond:
+        precond_bench(dev, args.steps)
         return
     if args.stream_probe:
         print(json.dumps({"stream_ceiling_gbs": stream_ceilings(wri, dev)}), flush=True)

@@ -463,6 +463,35 @@ typedef struct {
 /* Fills *out; WRI_EINVAL if no timed call has completed on this thread. */
 int wri_kernel_times(wri_timing* out);
 
+/* Objective and gradient with the preconditioned CGLS (row f4 of the build:
+ * fewer iterations).  Beyond the paper, whose only reducer of the iteration
+ * count is the adaptive tolerance of Algorithm 2: S is preconditioned on the
+ * right by one multigrid V(1,1) cycle of the complex-shifted Helmholtz
+ * operator A_beta = L_h + diag(omega^2 (1 - i beta) m - i omega b), beta = 1/2
+ * (damped Jacobi 0.7, trilinear prolongation, restriction P^T / 8, grids
+ * halved while every axis has >= 4 cells and the level > 512 cells, 4 Jacobi
+ * steps on the coarsest level), i.e. CGLS on min ||S M y - b||, x = M y.  The
+ * minimiser is the one of eq. SimpObj; S has the printed source column -e
+ * (weight 1); a system stops when ||S^H r|| <= rtol ||S^H b|| (the true
+ * normal residual, as in wri_solve).  All systems of a grid iterate in
+ * lockstep, chunks of iterations replay from a hipGraph.
+ *   Arguments and results as in wri_objective_grad, except:
+ *   J_out, grad  may be NULL (a solve only); grad[g] DEVICE float32 n(g)
+ *   flags        0 or WRI_FLAG_NO_GRAPH (anything else: WRI_EINVAL)
+ *   ws           DEVICE workspace of ws_bytes >= wri_precond_workspace_bytes()
+ *                (about 9 complex vectors per system plus 4/7 of one for the
+ *                coarse levels)
+ *   res[k].relres is sqrt(||S^H r||^2 / ||S^H b||^2), res[k].alpha the CGLS
+ *   unknown and res[k].alpha_ls = (A u)[src] in float64 (ESTIMATE).
+ * Statuses: converged, max_iter, breakdown, zero_rhs. */
+size_t wri_precond_workspace_bytes(const wri_grid* grids, int32_t n_grids, const wri_system* sys,
+                                   int32_t n_sys, int32_t mode);
+int wri_objective_grad_precond(const wri_grid* grids, int32_t n_grids, const float* const* m,
+                               const wri_system* sys, int32_t n_sys, int32_t mode, int32_t max_iter,
+                               int32_t flags, double* J_out, float* const* grad,
+                               wri_c32* const* u_out, wri_result* res,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* Streaming bandwidth probe (a measurement helper, not a step of the method):
  * one grid-stride kernel with the HBM access mix of a fused CGLS launch and
  * none of its arithmetic, the practical bandwidth ceiling that the fused

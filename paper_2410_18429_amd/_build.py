@@ -11,7 +11,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwri.so")
-SOURCES = ["kernels.hip", "capi.hip", "outer.hip", "fwi.hip", "resample.hip", "offgrid.hip", "probe.hip"]
+SOURCES = ["kernels.hip", "capi.hip", "outer.hip", "fwi.hip", "resample.hip", "offgrid.hip", "probe.hip", "precond.hip"]
 ARCH = os.environ.get("WRI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -146,6 +146,12 @@ def lib() -> ctypes.CDLL:
     L.wri_version.restype = c_int
     L.wri_kernel_times.argtypes = [POINTER(WriTiming)]
     L.wri_kernel_times.restype = c_int
+    L.wri_precond_workspace_bytes.argtypes = [POINTER(WriGrid), c_int32, POINTER(WriSystem), c_int32, c_int32]
+    L.wri_precond_workspace_bytes.restype = c_size_t
+    L.wri_objective_grad_precond.argtypes = [POINTER(WriGrid), c_int32, pp, POINTER(WriSystem), c_int32, c_int32,
+                                             c_int32, c_int32, POINTER(c_double), pp, pp, POINTER(WriResult), vp,
+                                             c_size_t, vp]
+    L.wri_objective_grad_precond.restype = c_int
     L.wri_stream_probe_bytes.argtypes = [c_int32, ctypes.c_int64]
     L.wri_stream_probe_bytes.restype = c_size_t
     L.wri_stream_probe.argtypes = [c_int32, ctypes.c_int64, c_int32, vp, c_size_t, vp, POINTER(c_double)]
@@ -194,7 +200,8 @@ def lib() -> ctypes.CDLL:
     return L
 
 
-EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_solve_noalloc", "wri_stream_probe_bytes",
+EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_solve_noalloc", "wri_precond_workspace_bytes",
+            "wri_objective_grad_precond", "wri_stream_probe_bytes",
             "wri_stream_probe", "wri_objective_grad", "estimate_source",
             "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version",
             "wri_tv_workspace_bytes", "wri_tv", "wri_lbfgs_workspace_bytes", "wri_lbfgs_direction",
@@ -351,6 +358,35 @@ def solve(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=None, return_u
                            ws.numel(), _stream(batch.device))
     _check(code)
     return u_out, _results(res, batch.nsys)
+
+
+def objective_grad_precond(batch: Batch, mode=None, max_iter=20000, flags=0, u_out=None, grad_out=None,
+                           with_grad=True):
+    """wri_objective_grad_precond: the V-cycle-preconditioned CGLS.  Returns
+    (J or None, per-grid gradients or None, results); u_out as in solve()."""
+    mode = batch.mode if mode is None else mode
+    grads = None
+    gptr = None
+    if with_grad:
+        grads = grad_out or [torch.empty(batch.grid_cells(g), dtype=torch.float32, device=batch.device)
+                             for g in range(len(batch.grids_py))]
+        gptr = (c_void_p * max(1, len(grads)))(*[c_void_p(g.data_ptr()) for g in grads])
+    nbytes = lib().wri_precond_workspace_bytes(batch.cgrids, len(batch.grids_py), batch.csys, batch.nsys, mode)
+    if nbytes == 0:
+        raise WriError(EINVAL, last_error())
+    key = ("precond", mode)
+    ws = batch._ws.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=batch.device)
+        batch._ws[key] = ws
+    res = (WriResult * max(1, batch.nsys))()
+    J = c_double(0.0)
+    code = lib().wri_objective_grad_precond(batch.cgrids, len(batch.grids_py), batch.m_ptrs(), batch.csys,
+                                            batch.nsys, mode, int(max_iter), int(flags),
+                                            ctypes.byref(J) if with_grad else None, gptr, _u_ptrs(batch, u_out),
+                                            res, c_void_p(ws.data_ptr()), ws.numel(), _stream(batch.device))
+    _check(code)
+    return (J.value if with_grad else None), grads, _results(res, batch.nsys)
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # WRI_NOALLOC_SCRATCH_BYTES
