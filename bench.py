@@ -60,14 +60,11 @@ def kernel_label(dominant, pf):
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "1fde0396a50c26bc",
+    "sources_sha256": "e949af9a8634210f",
     "tiles": {
-        "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1842277.7, "write_kib": 1573194.8},
-                       "fwd": {"fetch_kib": 1047779.5, "write_kib": 786706.3},
-                       "adj": {"fetch_kib": 1032439.0, "write_kib": 1573111.5}},
-        "4,2,32,2,4": {"fwd_x": {"fetch_kib": 1909017.8, "write_kib": 1573229.9},
-                       "fwd": {"fetch_kib": 1039976.3, "write_kib": 786673.1},
-                       "adj": {"fetch_kib": 1054648.9, "write_kib": 1573149.4}},
+        "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1838705.6, "write_kib": 1573194.1},
+                       "fwd": {"fetch_kib": 991201.6, "write_kib": 786618.8},
+                       "adj": {"fetch_kib": 1036113.8, "write_kib": 1573108.6}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
@@ -332,12 +329,13 @@ def tail_probe(dev, tiles, k1=600, k2=800):
     return out
 
 
-def precond_bench(dev, steps, rtols=(1e-4, 1e-5), ref_rtol=1e-8, sample=(0, 16, 32, 47)):
+def precond_bench(dev, steps, rtols=(1e-4, 1e-5), ref_rtol=1e-7, sample=(0, 16, 32, 47)):
     """The 128^3 workload (48 systems) solved by the plain batched CGLS (the
     headline method) and by the V-cycle-preconditioned CGLS (row f4): seconds
     per objective-and-gradient evaluation, iteration counts, and the wavefield
     and source-weight errors of both against a tight preconditioned solve
-    (rtol 1e-8) of the same systems, on sampled systems."""
+    (rtol 1e-7, about what float32 storage resolves) of the same systems, on
+    sampled systems."""
     import torch
     import wri_synth
     from paper_2410_18429_amd import wri
@@ -362,7 +360,7 @@ def precond_bench(dev, steps, rtols=(1e-4, 1e-5), ref_rtol=1e-8, sample=(0, 16, 
         return [u[k].cpu().numpy().astype(np.complex128) for k in sample], [res[k]["alpha_ls"] for k in sample], res
 
     b.set_rtol(ref_rtol)
-    ref_u, ref_a, ref_res = fields(lambda u: wri.objective_grad_precond(b, u_out=u, max_iter=100000))
+    ref_u, ref_a, ref_res = fields(lambda u: wri.objective_grad_precond(b, u_out=u, max_iter=5000))
     log(f"[precond] reference: rtol {ref_rtol:g}, iterations {[ref_res[k]['iters'] for k in sample]}")
 
     def errs(us, als):
@@ -761,6 +759,9 @@ def main():
     ap.add_argument("--precond", action="store_true",
                     help="the V-cycle-preconditioned solver against the plain one on the 128^3 workload "
                          "(time per evaluation, iterations, errors against a tight solve), one JSON line")
+    ap.add_argument("--precond-evals", type=int, default=0,
+                    help="profiling run: this many preconditioned objective-and-gradient evaluations of the 128^3 "
+                         "workload at rtol 1e-4, one JSON line")
     ap.add_argument("--stream-probe", action="store_true",
                     help="only the streaming probe of every access mix (profiling run), one JSON line")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -790,6 +791,19 @@ def main():
         return
     if args.precond:
         precond_bench(dev, args.steps)
+        return
+    if args.precond_evals > 0:
+        prob = wri_synth.make_config("differentiation", seed=0)
+        b = wri.Batch(prob, device=dev)
+        recs = []
+        for i in range(args.precond_evals):
+            t0 = time.perf_counter()
+            J, _, res = wri.objective_grad_precond(b)
+            torch.cuda.synchronize()
+            recs.append({"seconds": round(time.perf_counter() - t0, 4), "J": J,
+                         "iters_mean": float(np.mean([r["iters"] for r in res]))})
+            print(f"[precond] evaluation {i}: {json.dumps(recs[-1])}", file=sys.stderr, flush=True)
+        print(json.dumps({"mode": "precond_evals", "evaluations": recs}), flush=True)
         return
     if args.stream_probe:
         print(json.dumps({"stream_ceiling_gbs": stream_ceilings(wri, dev)}), flush=True)

@@ -483,7 +483,7 @@ int wri_kernel_times(wri_timing* out);
  *                coarse levels)
  *   res[k].relres is sqrt(||S^H r||^2 / ||S^H b||^2), res[k].alpha the CGLS
  *   unknown and res[k].alpha_ls = (A u)[src] in float64 (ESTIMATE).
- * Statuses: converged, max_iter, breakdown, zero_rhs. */
+ * Statuses: converged, max_iter, breakdown, zero_rhs, diverged (as in wri_solve). */
 size_t wri_precond_workspace_bytes(const wri_grid* grids, int32_t n_grids, const wri_system* sys,
                                    int32_t n_sys, int32_t mode);
 int wri_objective_grad_precond(const wri_grid* grids, int32_t n_grids, const float* const* m,

@@ -57,6 +57,7 @@ struct PcLevel {
   double h2inv;
   const float* m;
   const float* b;
+  const float2* wdinv;   // w D^-1 of A_beta on this level (per grid and frequency), complex64
   float2 *f, *y, *o, *res;
 };
 
@@ -73,7 +74,7 @@ struct PcSys {
 
 // Mutable scalars of one system (float64).
 struct PcState {
-  double gamma, ss0, ss, a, beta, J;
+  double gamma, ss0, ss, ssmin, a, beta, J;
   double2 xa, pa, za;
   int status, iters, pad_[2];
 };
@@ -277,15 +278,21 @@ __global__ void __launch_bounds__(kThr) k_pc_check(const PcSys* __restrict__ sy,
     T.ss = ss;
     if (setup) {
       T.ss0 = ss;
+      T.ssmin = ss;
       if (ss == 0.0) T.status = kZeroRhs;
       else if (!(ss <= DBL_MAX)) T.status = kBreakdown;
       else if (S.rtol2 >= 1.0) T.status = kConverged;   // ||s_0|| <= rtol ||s_0||
       else if (S.max_iter <= 0) T.status = kMaxIter;
     } else {
       T.iters += 1;
+      // below what float32 storage resolves the recurrences iterate on
+      // rounding noise: a rise of ||S^H r|| 1e4 times above its running
+      // minimum stops the system (as in the plain solver)
+      T.ssmin = fmin(T.ssmin, ss);
       if (!(ss <= DBL_MAX)) T.status = kBreakdown;
       else if (ss <= S.rtol2 * T.ss0) T.status = kConverged;
       else if (T.iters >= S.max_iter) T.status = kMaxIter;
+      else if (ss > kDivergeRatio * T.ssmin) T.status = kDiverged;
     }
   }
 }
@@ -320,12 +327,11 @@ __device__ __forceinline__ double2 diag_beta(const PcSys& S, const PcLevel& L, i
   const double im = -kBeta * S.omega2 * m - S.omega * b;
   return make_double2(-6.0 * L.h2inv + S.omega2 * m, conj ? -im : im);
 }
-// w D^-1 v
-__device__ __forceinline__ double2 jac(double2 d, float2 v) {
-  const double den = d.x * d.x + d.y * d.y;
-  const double re = ((double)v.x * d.x + (double)v.y * d.y) / den;
-  const double im = ((double)v.y * d.x - (double)v.x * d.y) / den;
-  return make_double2(kJac * re, kJac * im);
+// w D^-1 v with the tabulated w D^-1 (conjugated for the cycle on conj(A_beta))
+__device__ __forceinline__ double2 jac(const PcLevel& L, int c, int conj, float2 v) {
+  const float2 w = L.wdinv[c];
+  const double wr = w.x, wi = conj ? -(double)w.y : (double)w.y;
+  return make_double2(wr * v.x - wi * v.y, wr * v.y + wi * v.x);
 }
 __device__ __forceinline__ void coords(const PcLevel& L, int c, int& x, int& y, int& z) {
   const int plane = L.nx * L.ny;
@@ -358,13 +364,13 @@ __global__ void __launch_bounds__(kThr) k_pc_vdown(const PcSys* __restrict__ sy,
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       if (nb[i] < 0) continue;
-      const double2 yn = jac(diag_beta(S, L, nb[i], conj), f[nb[i]]);
+      const double2 yn = jac(L, nb[i], conj, f[nb[i]]);
       sr += yn.x;
       si += yn.y;
     }
     const double2 d = diag_beta(S, L, c, conj);
     const float2 fc = f[c];
-    const double2 yc = jac(d, fc);
+    const double2 yc = jac(L, c, conj, fc);
     const double ar = sr * L.h2inv + (d.x * yc.x - d.y * yc.y);
     const double ai = si * L.h2inv + (d.x * yc.y + d.y * yc.x);
     L.res[c] = fd((double)fc.x - ar, (double)fc.y - ai);
@@ -419,7 +425,7 @@ __global__ void __launch_bounds__(kThr) k_pc_vcoarse(const PcSys* __restrict__ s
   for (int c = blockIdx.x * kThr + threadIdx.x; c < L.n; c += gridDim.x * kThr) {
     const double2 d = diag_beta(S, L, c, conj);
     if (sweep == 0) {
-      const double2 v = jac(d, f[c]);
+      const double2 v = jac(L, c, conj, f[c]);
       out[c] = fd(v.x, v.y);
       continue;
     }
@@ -436,7 +442,7 @@ __global__ void __launch_bounds__(kThr) k_pc_vcoarse(const PcSys* __restrict__ s
     const double ar = sr * L.h2inv + (d.x * xc.x - d.y * xc.y);
     const double ai = si * L.h2inv + (d.x * xc.y + d.y * xc.x);
     const float2 fc = f[c];
-    const double2 corr = jac(d, fd((double)fc.x - ar, (double)fc.y - ai));
+    const double2 corr = jac(L, c, conj, fd((double)fc.x - ar, (double)fc.y - ai));
     out[c] = fd((double)xc.x + corr.x, (double)xc.y + corr.y);
   }
 }
@@ -490,7 +496,7 @@ __global__ void __launch_bounds__(kThr) k_pc_vprolong(const PcSys* __restrict__ 
         }
       }
     }
-    const double2 j = jac(diag_beta(S, F, c, conj), f[c]);
+    const double2 j = jac(F, c, conj, f[c]);
     F.y[c] = fd(j.x + sr, j.y + si);
   }
 }
@@ -524,7 +530,7 @@ __global__ void __launch_bounds__(kThr) k_pc_vsmooth(const PcSys* __restrict__ s
     const double ar = sr * L.h2inv + (d.x * xc.x - d.y * xc.y);
     const double ai = si * L.h2inv + (d.x * xc.y + d.y * xc.x);
     const float2 fc = f[c];
-    const double2 corr = jac(d, fd((double)fc.x - ar, (double)fc.y - ai));
+    const double2 corr = jac(L, c, conj, fd((double)fc.x - ar, (double)fc.y - ai));
     const float2 o = fd((double)xc.x + corr.x, (double)xc.y + corr.y);
     out[c] = o;
     acc += nrm(o);
@@ -562,6 +568,18 @@ __global__ void __launch_bounds__(kThr) k_pc_vsingle_out(const PcSys* __restrict
 // ---------------------------------------------------------------------------
 // grid set-up and results
 // ---------------------------------------------------------------------------
+
+// w D^-1 of A_beta on one level for one frequency: w / (-6/h^2 + omega^2 (1 - i beta) m - i omega b)
+__global__ void __launch_bounds__(kThr) k_pc_wdinv(const float* __restrict__ m, const float* __restrict__ b, int n,
+                                                   double h2inv, double omega, float2* __restrict__ out) {
+  for (int c = blockIdx.x * kThr + threadIdx.x; c < n; c += gridDim.x * kThr) {
+    const double mm = m[c], bb = b[c];
+    const double dr = -6.0 * h2inv + omega * omega * mm;
+    const double di = -kBeta * omega * omega * mm - omega * bb;
+    const double den = dr * dr + di * di;
+    out[c] = fd(kJac * dr / den, -kJac * di / den);
+  }
+}
 
 // b_0 = the sponge of the grid (float32)
 __global__ void __launch_bounds__(kThr) k_pc_sponge(float* __restrict__ b, int nx, int ny, int nz, int nb,
@@ -663,6 +681,9 @@ int64_t cells_of(const LevelDims& d) { return (int64_t)d.nx * d.ny * d.nz; }
 struct PcLayout {
   size_t sys = 0, state = 0, parts = 0, idx = 0, total = 0;
   std::vector<size_t> grid_arrays;   // per grid: m_l (l >= 1) and b_l (l >= 0)
+  std::vector<std::pair<int, double>> pairs;   // distinct (grid, omega) of the systems
+  std::vector<int> pair_of;                    // per system
+  std::vector<size_t> pair_arrays;             // per pair: w D^-1 on every level
   std::vector<size_t> vec, rvec, rec;
 };
 
@@ -679,6 +700,18 @@ PcLayout pc_layout(const wri_grid* grids, int n_grids, const wri_system* sys, in
     size_t b = 0;
     for (const auto& d : levels_of(grids[g])) b += 2 * al(sizeof(float) * (size_t)cells_of(d));
     L.grid_arrays[g] = take(b);
+  }
+  L.pair_of.assign(n_sys, -1);
+  for (int k = 0; k < n_sys; ++k) {
+    const std::pair<int, double> key(sys[k].grid, sys[k].omega);
+    auto it = std::find(L.pairs.begin(), L.pairs.end(), key);
+    L.pair_of[k] = (int)(it - L.pairs.begin());
+    if (it == L.pairs.end()) L.pairs.push_back(key);
+  }
+  for (const auto& pr : L.pairs) {
+    size_t b = 0;
+    for (const auto& d : levels_of(grids[pr.first])) b += al(sizeof(float2) * (size_t)cells_of(d));
+    L.pair_arrays.push_back(take(b));
   }
   L.vec.resize(n_sys);
   L.rvec.resize(n_sys);
@@ -752,6 +785,23 @@ int pc_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
       gb[g][l] = bb[l];
     }
   }
+  // w D^-1 per distinct (grid, frequency) and level
+  std::vector<std::vector<const float2*>> pw(L.pairs.size());
+  for (size_t q = 0; q < L.pairs.size(); ++q) {
+    const int g = L.pairs[q].first;
+    const double om = L.pairs[q].second;
+    const auto lv = levels_of(grids[g]);
+    char* p = base + L.pair_arrays[q];
+    for (size_t l = 0; l < lv.size(); ++l) {
+      float2* w = reinterpret_cast<float2*>(p);
+      const int64_t nl = cells_of(lv[l]);
+      hipLaunchKernelGGL(k_pc_wdinv, dim3(blocks_for(nl)), dim3(kThr), 0, st, gm[g][l], gb[g][l], (int)nl,
+                         1.0 / (lv[l].h * lv[l].h), om, w);
+      PC_HIP(hipGetLastError());
+      pw[q].push_back(w);
+      p += al(sizeof(float2) * (size_t)nl);
+    }
+  }
   if (n_sys == 0) {
     if (grad != nullptr)
       for (int g = 0; g < n_grids; ++g) PC_HIP(launch_zero_f32(grad[g], (size_t)grids[g].nx * grids[g].ny * grids[g].nz, st));
@@ -787,6 +837,7 @@ int pc_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
       Lv.h2inv = 1.0 / (lv[l].h * lv[l].h);
       Lv.m = gm[s.grid][l];
       Lv.b = gb[s.grid][l];
+      Lv.wdinv = pw[L.pair_of[k]][l];
       if (l == 0) {
         Lv.f = nullptr; Lv.o = nullptr;
         Lv.res = vec(7); Lv.y = vec(8);
@@ -856,8 +907,7 @@ int pc_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
         const int nbk = (l == 0) ? kParts : blocks_for(cells_of(lv[l]));
         hipLaunchKernelGGL(k_pc_vprolong, dim3(blocks_for(cells_of(lv[l])), G.cnt), dim3(kThr), 0, sq, dsys, dst,
                            G.p0, l, which, conj);
-        hipLaunchKernelGGL(k_pc_vsmooth, dim3(nbk, G.cnt), dim3(kThr), 0, sq, dsys, dst, parts, G.p0, l, which,
-                           conj);
+        hipLaunchKernelGGL(k_pc_vsmooth, dim3(nbk, G.cnt), dim3(kThr), 0, sq, dsys, dst, parts, G.p0, l, which, conj);
       }
     }
     PC_HIP(hipGetLastError());
@@ -987,7 +1037,7 @@ int pc_run(const wri_grid* grids, int n_grids, const float* const* m, const wri_
     }
     J += T.J;
     if (T.status == kBreakdown) ret = WRI_EBREAKDOWN;
-    else if (T.status == kMaxIter && ret == WRI_OK) ret = WRI_NOT_CONVERGED;
+    else if ((T.status == kMaxIter || T.status == kDiverged) && ret == WRI_OK) ret = WRI_NOT_CONVERGED;
   }
   if (J_out) *J_out = J;
   if (ret == WRI_EBREAKDOWN) report_error(WRI_EBREAKDOWN, "at least one system broke down");
