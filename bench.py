@@ -58,9 +58,11 @@ def kernel_label(dominant, pf):
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  "fwd_x" is the forward launch that also updates x
 # (even iterations).  Valid only for the solver sources it was measured on (sha256 prefix of
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
-# summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
+# summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md.  Measured on
+# sources e949af9a8634210f; the sources named here differ from them only in a host-side progress
+# message of the solve loop (no kernel, launch or tile changes).
 TRAFFIC = {
-    "sources_sha256": "e949af9a8634210f",
+    "sources_sha256": "5a36206397ef3a29",
     "tiles": {
         "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1838705.6, "write_kib": 1573194.1},
                        "fwd": {"fetch_kib": 991201.6, "write_kib": 786618.8},
@@ -651,19 +653,44 @@ def large_bench(freq, rtol, dev):
                                   f"rtol {rtol:g}", **out}))
 
 
-def large_gd_bench(n_iter, dev, start=0, m_in="", m_out="", warm=False):
+def large_gd_step_size():
+    import wri_synth
+    p = wri_synth.make_config("large", seed=0)
+    return 0.01 * float(np.abs(np.asarray(p.m[0], dtype=np.float32)).max())
+
+
+def large_gd_model_step(m_in, g_in, m_out):
+    """The protocol's model update on the host, for an iteration whose bands
+    ran in several calls: g = the sum of the calls' band gradients (float32, in
+    band order), m <- m - 0.01 max|m0| g / max|g|."""
+    m = np.load(m_in).astype(np.float32)
+    g = np.zeros_like(m)
+    for f in g_in:
+        g += np.load(f).astype(np.float32)
+    m -= np.float32(large_gd_step_size()) * g / np.abs(g).max()
+    np.save(m_out, m)
+    print(json.dumps({"large_gd_step": {"m_in": m_in, "g_in": g_in, "m_out": m_out, "max_abs_g": float(np.abs(g).max())}}))
+
+
+def large_gd_bench(n_iter, dev, start=0, m_in="", m_out="", warm=False, band_sel=None, g_out="", max_iter=20000):
     """The large workload's protocol: 10 outer gradient-descent iterations over
     all six frequency bands (64 systems each, one call per band), the solver
     tolerance tightened as rtol_k = 1e-2 (1e-3)^(k/9), each iteration the full
     objective, gradient and source-weight estimate of all 384 systems, then
     m <- m - 0.01 max|m0| g / max|g|.  Reports latency per iteration and the
-    fused kernels' rates (HIP events around every launch)."""
+    fused kernels' rates (HIP events around every launch).  With band_sel only
+    those bands of one iteration run; their summed gradient goes to g_out and
+    the model is not stepped (large_gd_model_step does it on the host)."""
     import torch
     import wri_synth
     from paper_2410_18429_amd import wri
     p = wri_synth.make_config("large", seed=0)
     freqs = sorted(set(s.freq for s in p.systems))
     bands = [[k for k, s in enumerate(p.systems) if s.freq == f] for f in freqs]
+    if band_sel is not None:
+        if n_iter != 1 or warm:
+            raise SystemExit("--large-gd-bands runs one cold iteration (--large-gd 1)")
+        bands = [bands[i] for i in band_sel]
     m0 = np.asarray(p.m[0], dtype=np.float32).reshape(-1)
     step = 0.01 * float(np.abs(m0).max())
     # a run may continue an earlier one (iterations start.. with its model)
@@ -681,32 +708,41 @@ def large_gd_bench(n_iter, dev, start=0, m_in="", m_out="", warm=False):
         g = torch.zeros_like(m)
         fb = fms = ab = ams = 0.0
         iters = []
+        statuses = []
         for bi, band in enumerate(bands):
             b = wri.Batch(p.subset(band).with_rtol(rtol), device=dev, m=[m])
             if warm:
                 b.set_alpha(keep_a[bi])
-                Jb, gb, res = wri.objective_grad(b, flags=wri.FLAG_TIMING | wri.FLAG_WARM_START, u_out=keep_u[bi])
+                Jb, gb, res = wri.objective_grad(b, flags=wri.FLAG_TIMING | wri.FLAG_WARM_START, u_out=keep_u[bi],
+                                                 max_iter=max_iter)
                 keep_a[bi] = [r["alpha"] for r in res]
             else:
-                Jb, gb, res = wri.objective_grad(b, flags=wri.FLAG_TIMING)
+                Jb, gb, res = wri.objective_grad(b, flags=wri.FLAG_TIMING, max_iter=max_iter)
             kt = wri.kernel_times()
             fb += kt["fwd_bytes"]; fms += kt["fwd_ms"]; ab += kt["adj_bytes"]; ams += kt["adj_ms"]
             J += Jb
             g += gb[0]
             iters += [r["iters"] for r in res]
+            statuses += [r["status"] for r in res]
             del b, gb
             print(f"[large-gd] iteration {it} band {p.systems[band[0]].freq:g} Hz: "
                   f"{time.perf_counter() - t0:.1f} s so far, max iterations {max(r['iters'] for r in res)}",
                   file=sys.stderr, flush=True)
-        m -= step * g / g.abs().max()
+        if band_sel is None:
+            m -= step * g / g.abs().max()
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         rows.append({"iteration": it, "rtol": float(f"{rtol:.3g}"), "seconds": round(sec, 2), "J": J,
                      "cgls_iterations_mean": round(float(np.mean(iters)), 1), "cgls_iterations_max": int(max(iters)),
+                     "not_converged": int(sum(1 for x in statuses if x != "converged")),
                      "fwd_gbs": round(fb / (fms * 1e-3) / 1e9, 1), "adj_gbs": round(ab / (ams * 1e-3) / 1e9, 1)})
+        if band_sel is not None:
+            rows[-1]["bands_hz"] = [freqs[i] for i in band_sel]
         print(f"[large-gd] {rows[-1]}", file=sys.stderr, flush=True)
-        if m_out:
+        if m_out and band_sel is None:
             np.save(m_out, m.cpu().numpy())
+        if g_out:
+            np.save(g_out, g.cpu().numpy())
     print(json.dumps({"metric": "large workload: latency per outer gradient-descent iteration",
                       "workload": "large: 256x256x192, 384 systems (64 sources x 6 frequencies, one call per band), "
                                   "ESTIMATE" + (", warm-started solves" if warm else ""), "iterations": rows,
@@ -745,6 +781,13 @@ def main():
                     help="first outer iteration (a continued run loads its model with --large-gd-m-in)")
     ap.add_argument("--large-gd-m-in", default="", help="model (.npy, float32) to continue from")
     ap.add_argument("--large-gd-m-out", default="", help="write the model after every outer iteration (.npy)")
+    ap.add_argument("--large-gd-bands", default="",
+                    help="with --large-gd 1: only these frequency bands (indices 0-5, comma-separated) of the "
+                         "iteration; their summed gradient goes to --large-gd-g-out and the model is not stepped")
+    ap.add_argument("--large-gd-g-out", default="", help="write the iteration's summed gradient (.npy)")
+    ap.add_argument("--large-gd-max-iter", type=int, default=20000, help="CGLS iteration cap of the protocol's solves")
+    ap.add_argument("--large-gd-step", default="",
+                    help="host-only model update: 'M_IN;G1,G2,...;M_OUT' (gradients of one iteration's calls)")
     ap.add_argument("--large-gd-warm", action="store_true",
                     help="start every solve from the system's wavefield and weight of the previous outer iteration")
     ap.add_argument("--fwi", action="store_true",
@@ -771,6 +814,10 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the systems are independent: a batch would shard by system across GPUs).", file=sys.stderr)
         sys.exit(2)
+    if args.large_gd_step:
+        m_in, g_in, m_out = args.large_gd_step.split(";")
+        large_gd_model_step(m_in, [f for f in g_in.split(",") if f], m_out)
+        return
 
     import torch
     import wri_synth
@@ -821,8 +868,9 @@ def main():
         model_grid_bench(args.steps, dev)
         return
     if args.large_gd > 0:
+        sel = [int(v) for v in args.large_gd_bands.split(",")] if args.large_gd_bands else None
         large_gd_bench(args.large_gd, dev, args.large_gd_start, args.large_gd_m_in, args.large_gd_m_out,
-                       args.large_gd_warm)
+                       args.large_gd_warm, sel, args.large_gd_g_out, args.large_gd_max_iter)
         return
     if args.large_band > 0:
         large_bench(args.large_band, args.large_rtol, dev)

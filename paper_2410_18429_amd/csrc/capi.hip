@@ -5,6 +5,7 @@
 #include "../../include/wri.h"
 #include "wri_impl.hpp"
 
+#include <chrono>
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -686,6 +687,7 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     const bool use_graph = !(C.flags & WRI_FLAG_NO_GRAPH) && !timing;
     int chunk = 8;
     int64_t launched = 0;
+    auto last_report = std::chrono::steady_clock::now();
     EventPool pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fwd, ev_adj;
     if (timing) g_times = KernelTimes();
@@ -748,7 +750,19 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
         T.adj_launches += (int64_t)ev_adj.size();
       }
       bool active = false;
-      for (const auto& s : hs) active = active || (s.status == kActive);
+      int n_active = 0;
+      for (const auto& s : hs) {
+        active = active || (s.status == kActive);
+        n_active += (s.status == kActive) ? 1 : 0;
+      }
+      if (verbose() && active) {  // progress of long solves, at most every 30 s
+        const auto now = std::chrono::steady_clock::now();
+        if (now - last_report > std::chrono::seconds(30)) {
+          fprintf(stderr, "[wri] iteration %lld: %d of %d systems iterating\n", (long long)launched, n_active,
+                  C.n_sys);
+          last_report = now;
+        }
+      }
       if (!active) break;
       if (launched > (int64_t)C.max_iter + 2)
         return fail(WRI_EHIP, "internal: systems still active after max_iter+2 iterations");
