@@ -459,6 +459,48 @@ int set_config(Ctx& C, const TileCfg& cfg) {
 
 const TileCfg& cur_cfg(const Ctx& C) { return C.tiling.front().cfg; }
 
+// Convergence tail: once the systems still iterating hold few cells, the
+// tiling tuned for the full batch leaves compute units idle (one 128^3 system
+// is 64 workgroups of the 64 x 16 x 32 tile on 256 compute units), so the
+// solve switches, at an iteration boundary, to a finer tile of the same march.
+// Only for the recomputed-t march chosen by the autotuner; WRI_TAIL_TILE
+// ("w,ry,tz,pf[,order]", or "0" for no switch) and WRI_TAIL_CELLS override the
+// tile and the threshold (tests, experiments).
+constexpr TileCfg kTailCfg{4, 2, 16, 2, 4};
+constexpr int64_t kTailCells = 0;
+bool tail_config(const TileCfg& main, bool forced_main, TileCfg* out, int64_t* max_cells) {
+  *max_cells = kTailCells;
+  if (const char* e = getenv("WRI_TAIL_CELLS"); e != nullptr && *e) *max_cells = atoll(e);
+  const char* e = getenv("WRI_TAIL_TILE");
+  if (e != nullptr && *e) {
+    if (*e == '0') return false;
+    TileCfg t{0, 0, 0, 0, 0};
+    const int got = sscanf(e, "%d,%d,%d,%d,%d", &t.w, &t.ry, &t.tz, &t.pf, &t.order);
+    if (got < 4 || !cfg_supported(t)) return false;
+    if (got == 4) t.order = 0;
+    // t is produced and consumed within one iteration, so any march may follow
+    *out = t;
+    return true;
+  }
+  if (forced_main || main.pf < 2) return false;
+  *out = kTailCfg;
+  return !(out->w == main.w && out->ry == main.ry && out->tz == main.tz && out->pf == main.pf &&
+           out->order == main.order);
+}
+
+// Switch the tiling between two iterations: the new group table, then the
+// partials of ||s||^2 that the next forward launch reads folded to the new tile
+// count.
+int switch_tiling(Ctx& C, const TileCfg& cfg) {
+  std::vector<int> n_old(C.hgd.size());
+  for (size_t gi = 0; gi < C.hgd.size(); ++gi) n_old[gi] = C.hgd[gi].ntiles;
+  const int rc = set_config(C, cfg);
+  if (rc != WRI_OK) return rc;
+  for (size_t gi = 0; gi < C.hgd.size(); ++gi)
+    WRI_HIP(launch_fold_partials(C.dsys, C.part_s, C.hgd[gi].rhs0, C.hgd[gi].nrhs, n_old[gi], C.hgd[gi].ntiles, C.st));
+  return WRI_OK;
+}
+
 // eager iteration with an event pair around the forward and adjoint launches
 int launch_iteration_timed(Ctx& C, int k, EventPool& pool, std::vector<std::pair<hipEvent_t, hipEvent_t>>& fwd,
                            std::vector<std::pair<hipEvent_t, hipEvent_t>>& adj) {
@@ -663,12 +705,14 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     C.groups.back().nrhs++;
   }
 
+  TileCfg main_cfg = kCands[0];  // the tile of the full batch (reported by the timing)
   if (C.n_sys > 0) {
     WRI_HIP(hipMemcpyAsync(C.dsys, C.hsys.data(), sizeof(SysDev) * C.n_sys, hipMemcpyHostToDevice, C.st));
     int rc = upload_receivers(C);
     if (rc != WRI_OK) return rc;
     TileCfg forced;
-    if (forced_tile(&forced)) rc = set_config(C, forced);
+    const bool is_forced = forced_tile(&forced);
+    if (is_forced) rc = set_config(C, forced);
     else if (!(C.flags & WRI_FLAG_NO_AUTOTUNE)) rc = autotune(C);
     else rc = set_config(C, kCands[0]);
     if (rc != WRI_OK) return rc;
@@ -688,6 +732,10 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     int chunk = 8;
     int64_t launched = 0;
     auto last_report = std::chrono::steady_clock::now();
+    main_cfg = cur_cfg(C);
+    TileCfg tail_cfg = main_cfg;
+    int64_t tail_cells = 0;
+    bool tail_pending = tail_config(main_cfg, is_forced, &tail_cfg, &tail_cells);
     EventPool pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fwd, ev_adj;
     if (timing) g_times = KernelTimes();
@@ -764,6 +812,20 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
         }
       }
       if (!active) break;
+      if (tail_pending) {
+        int64_t act_cells = 0;
+        for (int p = 0; p < C.n_sys; ++p)
+          if (hs[p].status == kActive) act_cells += cells(C.grids[C.sys[L.order[p]].grid]);
+        if (act_cells <= tail_cells) {
+          rc = switch_tiling(C, tail_cfg);
+          if (rc != WRI_OK) return rc;
+          tail_pending = false;
+          if (verbose())
+            fprintf(stderr, "[wri] iteration %lld: %d systems (%lld cells) iterating, tile w=%d ry=%d tz=%d pf=%d order=%d\n",
+                    (long long)launched, n_active, (long long)act_cells, tail_cfg.w, tail_cfg.ry, tail_cfg.tz,
+                    tail_cfg.pf, tail_cfg.order);
+        }
+      }
       if (launched > (int64_t)C.max_iter + 2)
         return fail(WRI_EHIP, "internal: systems still active after max_iter+2 iterations");
       chunk = std::min(chunk * 2, 128);
@@ -771,7 +833,7 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
   }
   if (C.flags & WRI_FLAG_TIMING) {
     if (!C.tiling.empty()) {
-      const TileCfg& c = cur_cfg(C);
+      const TileCfg& c = main_cfg;
       g_times.t.tile_w = c.w; g_times.t.tile_ry = c.ry; g_times.t.tile_tz = c.tz;
       g_times.t.tile_pf = c.pf; g_times.t.tile_order = c.order;
     }

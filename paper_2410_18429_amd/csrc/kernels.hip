@@ -299,6 +299,29 @@ hipError_t launch_warm_residual(const SysDev* sys, SysState* st, const double* p
   return hipGetLastError();
 }
 
+// A change of tiling between two iterations: the adjoint pass of the old
+// tiling left the partials of ||s_k||^2 in n_old slots per system.  They are
+// folded into slot 0 in the order in which the forward pass sums its slots
+// (lane 0's value of the same wave sum), and the slots up to n_new are
+// cleared, so the forward pass of the new tiling sums exactly the same
+// gamma_k.  grid = one 64-thread block per system of a group.
+__global__ void __launch_bounds__(64) k_fold_partials(const SysDev* __restrict__ sysv, double* __restrict__ part_s,
+                                                     int rhs0, int n_old, int n_new) {
+  double* __restrict__ p = part_s + sysv[rhs0 + blockIdx.x].slot_base;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n_old; i += 64) v += p[i];
+  v = wave_sum(v);
+  const int n = max(n_old, n_new);
+  for (int i = threadIdx.x; i < n; i += 64) p[i] = (i == 0) ? v : 0.0;
+}
+
+hipError_t launch_fold_partials(const SysDev* sys, double* part_s, int rhs0, int nrhs, int n_old, int n_new,
+                                hipStream_t s) {
+  if (nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_partials, dim3(nrhs), dim3(64), 0, s, sys, part_s, rhs0, n_old, n_new);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Tile geometry shared by the fused kernels
 // ---------------------------------------------------------------------------

@@ -108,6 +108,11 @@ hipError_t launch_init(const SysDev* sys, SysState* st, int nsys, hipStream_t s,
 // pass's partials (nparts per system), then r = b - S x0 (x0 = 0 when b = 0).
 hipError_t launch_warm_residual(const SysDev* sys, SysState* st, const double* part_s, const int* nparts,
                                 int nsys, hipStream_t s);
+// Before the first forward launch of a new tiling: the ||s||^2 partials of the
+// group's systems [rhs0, rhs0 + nrhs) folded from n_old tiles into slot 0,
+// slots up to n_new cleared.
+hipError_t launch_fold_partials(const SysDev* sys, double* part_s, int rhs0, int nrhs, int n_old, int n_new,
+                                hipStream_t s);
 // Fused CGLS launches over all groups (same tile shape c for all of them).
 // k: the iteration every active system of the launch is at (systems of one
 // call iterate in lockstep); selects the variant of the forward kernel that

@@ -185,6 +185,48 @@ def test_solve_parity_production_tiles_multi_slab(monkeypatch, mode):
         assert eg < 1e-3 and eg_max < 1e-3, (tile, eg, eg_max)
 
 
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+@pytest.mark.parametrize("tail", ["4,2,16,2,4", "8,1,16,1,4"])
+def test_tail_tiling_switch_parity(monkeypatch, mode, tail):
+    """The convergence-tail switch: the production tile 4,4,32,2,4 for the first
+    chunk of 8 iterations, then (threshold above the batch's cells) a finer
+    tile of the same recomputed-t march, or of the stored-t march, for the rest,
+    with the partials of ||s||^2 folded to the new tile count.  Against the
+    exact minimiser (u, alpha, J within 1e-4, g within 1e-3) and against the
+    same solve without the switch (iterations within 2 %, u within 5e-5: only
+    the summation order of ||t||^2 changes)."""
+    p = _multi_slab_problem()
+    if mode not in _MULTI_SLAB_REF:
+        _say(f"multi-slab oracle, mode={mode}")
+        _MULTI_SLAB_REF[mode] = oracle.objective_grad(p, mode=mode, normal_solver="woodbury")
+    ref = _MULTI_SLAB_REF[mode]
+    gref = ref["g"][0].reshape(-1)
+    monkeypatch.setenv("WRI_TILE", "4,4,32,2,4")
+    monkeypatch.setenv("WRI_TAIL_TILE", "0")
+    b = wri.Batch(p, device=DEV, mode=mode)
+    u0 = wri.alloc_wavefields(b)
+    _, _, r0 = wri.objective_grad(b, max_iter=60000, u_out=u0)
+    monkeypatch.setenv("WRI_TAIL_TILE", tail)
+    monkeypatch.setenv("WRI_TAIL_CELLS", str(1 << 40))
+    _say(f"tail switch 4,4,32,2,4 -> {tail}, mode={mode}")
+    u1 = wri.alloc_wavefields(b)
+    J, grads, res = wri.objective_grad(b, max_iter=60000, u_out=u1)
+    g = grads[0].cpu().numpy().astype(np.float64)
+    for i in range(len(p.systems)):
+        eu = rel(_np(u1[i]), ref["u"][i])
+        du = rel(_np(u1[i]), _np(u0[i]))
+        eJ = abs(res[i]["J"] - ref["J_sys"][i]) / ref["J_sys"][i]
+        _say(f"  sys {i}: iters {res[i]['iters']} (no switch {r0[i]['iters']}) u err {eu:.2e} "
+             f"vs no switch {du:.2e} J err {eJ:.2e}")
+        assert res[i]["status"] == "converged", res[i]
+        assert abs(res[i]["iters"] - r0[i]["iters"]) <= max(2, 0.02 * r0[i]["iters"]), i
+        assert eu < 1e-4 and eJ < 1e-4 and du < 5e-5, i
+        if mode == "estimate":
+            assert abs(res[i]["alpha_ls"] - ref["alpha"][i]) < 1e-4 * abs(ref["alpha"][i]), i
+    assert abs(J - ref["J"]) < 1e-4 * ref["J"]
+    assert rel(g, gref) < 1e-3
+
+
 def test_tiny_config_both_modes():
     _say("tiny config")
     p = wri_synth.make_config("tiny", data="none")
