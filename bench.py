@@ -391,8 +391,12 @@ def precond_bench(dev, steps, rtols=(1e-4, 1e-5), ref_rtol=1e-7, sample=(0, 16, 
 
 def stream_ceilings(wri, dev, n=1 << 27, reps=5):
     """GB/s of the library's streaming probe for each access mix (copy, forward,
-    forward with the x update, adjoint) over n complex64 elements per array."""
-    return {mix: wri.stream_probe(mix, n, reps, device=dev) for mix in ("copy", "fwd", "fwd_x", "adj")}
+    forward with the x update, adjoint) over n complex64 elements per array, and
+    of the forward mix in the fused kernels' tile order over the 48 grids of
+    128^3 of the workload ("fwd_tiles")."""
+    out = {mix: wri.stream_probe(mix, n, reps, device=dev) for mix in ("copy", "fwd", "fwd_x", "adj")}
+    out["fwd_tiles"] = wri.tile_probe(128, 128, 128, 48, reps, device=dev)
+    return out
 
 
 def awri_bench(name, updates, dev):
@@ -954,9 +958,10 @@ def main():
                 "fwd_gbs_full_batch": round(fwd_full_gbs, 1), "adj_gbs_full_batch": round(adj_full_gbs, 1),
                 "bytes_per_cell": bytes_note(kt["tile_pf"]), "tile": tile}
 
-    # practical streaming ceilings on this device: a plain grid-stride kernel with
-    # the access mix of each fused launch and none of its arithmetic
-    # (wri_stream_probe, 2^27 complex64 elements per array, best of five launches per variant)
+    # practical streaming ceilings on this device: a plain kernel with the access
+    # mix of each fused launch and none of its arithmetic (wri_stream_probe, 2^27
+    # complex64 elements per array, best of five launches per variant), and the
+    # forward mix in the fused kernels' own tile order (wri_tile_probe)
     ceil = stream_ceilings(wri, dev)
     pf = kt["tile_pf"]
     if dominant == "fwd":
@@ -973,6 +978,9 @@ def main():
     roofline["mix_ceiling_gbs"] = round(mix_ceiling, 1) if mix_ceiling else None
     roofline["frac_of_mix_ceiling"] = round(ach / mix_ceiling, 4) if mix_ceiling else None
     roofline["adj_frac_of_mix_ceiling_full_batch"] = round(adj_full_gbs / ceil["adj"], 4)
+    roofline["tile_order_ceiling_gbs"] = round(ceil["fwd_tiles"], 1)
+    roofline["frac_of_tile_order_ceiling_full_batch"] = round(ach_full / ceil["fwd_tiles"], 4)
+    roofline["adj_frac_of_tile_order_ceiling_full_batch"] = round(adj_full_gbs / ceil["fwd_tiles"], 4)
     log(f"[bench] stream ceilings {json.dumps(roofline['stream_ceiling_gbs'])}; dominant kernel at "
         f"{ach / ceil['copy']:.3f} of the copy, {roofline['frac_of_mix_ceiling']} of its own mix")
 

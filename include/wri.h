@@ -493,10 +493,9 @@ int wri_objective_grad_precond(const wri_grid* grids, int32_t n_grids, const flo
                                void* ws, size_t ws_bytes, void* stream);
 
 /* Streaming bandwidth probe (a measurement helper, not a step of the method):
- * one grid-stride kernel with the HBM access mix of a fused CGLS launch and
- * none of its arithmetic, the practical bandwidth ceiling that the fused
- * kernels' fraction of the 8 TB/s peak is set against.  Per complex64
- * element:
+ * a kernel with the HBM access mix of a fused CGLS launch and none of its
+ * arithmetic, the practical bandwidth ceiling that the fused kernels' fraction
+ * of the 8 TB/s peak is set against.  Per complex64 element:
  *   mix 0  copy: read a, write c                                    16 B
  *   mix 1  forward pass: read s, p, m; write p (no x update)         28 B
  *   mix 2  forward pass with the x update: + read x, p'; write x     52 B
@@ -507,12 +506,29 @@ int wri_objective_grad_precond(const wri_grid* grids, int32_t n_grids, const flo
  *            its contents are read and overwritten (values are arbitrary)
  *   gbs_out  HOST: bytes of the mix / the shortest launch time (HIP events on
  *            `stream`), in GB/s, the best over the probe's variants (one or
- *            four element pairs in flight per thread; ordinary or
- *            non-temporal stores)
+ *            four element pairs in flight per thread on a grid-stride grid of
+ *            8 blocks per compute unit, or one pair per thread on the full
+ *            grid; ordinary or non-temporal stores)
  * Returns WRI_EINVAL / WRI_ENOWS for bad arguments, WRI_EHIP on a HIP error. */
 size_t wri_stream_probe_bytes(int32_t mix, int64_t n);
 int wri_stream_probe(int32_t mix, int64_t n, int32_t reps, void* ws, size_t ws_bytes, void* stream,
                      double* gbs_out);
+
+/* The same probe in the fused kernels' access pattern: mix 1 (read a, b, m;
+ * write c; 28 B per cell) over n_sys grids of nx x ny x nz cells, one
+ * workgroup of 256 threads per (grid, 64 x 16 x 32 tile), blocks of the same
+ * tile of consecutive grids adjacent, marching z through its slab plane by
+ * plane (four cells per thread per plane), as the fused forward pass reads
+ * and writes its vectors.  m is one float32 array shared by the grids.
+ *   nx, ny, nz  multiples of 64, 16 and 32
+ *   ws          DEVICE workspace of ws_bytes >= wri_tile_probe_bytes(...),
+ *               contents read and overwritten (values arbitrary)
+ *   gbs_out     HOST: 28 B x n_sys x cells / the shortest of `reps` timed
+ *               launches (one warm-up launch first), in GB/s
+ * Returns WRI_EINVAL / WRI_ENOWS for bad arguments, WRI_EHIP on a HIP error. */
+size_t wri_tile_probe_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t n_sys);
+int wri_tile_probe(int32_t nx, int32_t ny, int32_t nz, int32_t n_sys, int32_t reps, void* ws, size_t ws_bytes,
+                   void* stream, double* gbs_out);
 
 /* Text of a return code; message of the last error on this thread. */
 const char* wri_strerror(int code);

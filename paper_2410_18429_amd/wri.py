@@ -156,6 +156,10 @@ def lib() -> ctypes.CDLL:
     L.wri_stream_probe_bytes.restype = c_size_t
     L.wri_stream_probe.argtypes = [c_int32, ctypes.c_int64, c_int32, vp, c_size_t, vp, POINTER(c_double)]
     L.wri_stream_probe.restype = c_int
+    L.wri_tile_probe_bytes.argtypes = [c_int32, c_int32, c_int32, c_int32]
+    L.wri_tile_probe_bytes.restype = c_size_t
+    L.wri_tile_probe.argtypes = [c_int32, c_int32, c_int32, c_int32, c_int32, vp, c_size_t, vp, POINTER(c_double)]
+    L.wri_tile_probe.restype = c_int
     L.wri_tv_workspace_bytes.argtypes = [POINTER(WriGrid)]
     L.wri_tv_workspace_bytes.restype = c_size_t
     L.wri_tv.argtypes = [POINTER(WriGrid), vp, c_double, c_double, POINTER(c_double), vp, vp, c_size_t, vp]
@@ -202,7 +206,7 @@ def lib() -> ctypes.CDLL:
 
 EXPORTED = ("wri_workspace_bytes", "wri_validate", "wri_solve", "wri_solve_noalloc", "wri_precond_workspace_bytes",
             "wri_objective_grad_precond", "wri_stream_probe_bytes",
-            "wri_stream_probe", "wri_objective_grad", "estimate_source",
+            "wri_stream_probe", "wri_tile_probe_bytes", "wri_tile_probe", "wri_objective_grad", "estimate_source",
             "wri_apply_helmholtz", "wri_kernel_times", "wri_strerror", "wri_last_error", "wri_version",
             "wri_tv_workspace_bytes", "wri_tv", "wri_lbfgs_workspace_bytes", "wri_lbfgs_direction",
             "wri_awri_workspace_bytes", "wri_awri", "wri_fwi_workspace_bytes", "wri_fwi_objective_grad",
@@ -231,6 +235,20 @@ def stream_probe(mix: str, n: int, reps: int = 5, device="cuda") -> float:
     out = c_double(0.0)
     _check(lib().wri_stream_probe(code, int(n), int(reps), c_void_p(ws.data_ptr()), nbytes,
                                   _stream(torch.device(device)), ctypes.byref(out)))
+    del ws
+    return out.value
+
+
+def tile_probe(nx: int, ny: int, nz: int, n_sys: int, reps: int = 5, device="cuda") -> float:
+    """wri_tile_probe: GB/s of a plain streaming kernel with the forward pass's
+    byte mix in the fused kernels' tile order over n_sys grids of nx x ny x nz."""
+    nbytes = lib().wri_tile_probe_bytes(int(nx), int(ny), int(nz), int(n_sys))
+    if nbytes == 0:
+        raise WriError(EINVAL, "bad tile probe shape")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    out = c_double(0.0)
+    _check(lib().wri_tile_probe(int(nx), int(ny), int(nz), int(n_sys), int(reps), c_void_p(ws.data_ptr()), nbytes,
+                                _stream(torch.device(device)), ctypes.byref(out)))
     del ws
     return out.value
 
