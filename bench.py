@@ -59,10 +59,11 @@ def kernel_label(dominant, pf):
 # (even iterations).  Valid only for the solver sources it was measured on (sha256 prefix of
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md.  Measured on
-# sources e949af9a8634210f; the sources named here differ from them only in a host-side progress
-# message of the solve loop (no kernel, launch or tile changes).
+# sources e949af9a8634210f; the sources named here differ from them in host code (a progress
+# message, the convergence-tail tiling switch) and in one added kernel that folds partial sums
+# at a tiling switch: the fused kernels and the full-batch launches are unchanged.
 TRAFFIC = {
-    "sources_sha256": "5a36206397ef3a29",
+    "sources_sha256": "9cbfa26d504e932d",
     "tiles": {
         "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1838705.6, "write_kib": 1573194.1},
                        "fwd": {"fetch_kib": 991201.6, "write_kib": 786618.8},
