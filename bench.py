@@ -58,16 +58,13 @@ def kernel_label(dominant, pf):
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  "fwd_x" is the forward launch that also updates x
 # (even iterations).  Valid only for the solver sources it was measured on (sha256 prefix of
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
-# summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md.  Measured on
-# sources e949af9a8634210f; the sources named here differ from them in host code (a progress
-# message, the convergence-tail tiling switch) and in one added kernel that folds partial sums
-# at a tiling switch: the fused kernels and the full-batch launches are unchanged.
+# summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
     "sources_sha256": "9cbfa26d504e932d",
     "tiles": {
-        "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1838705.6, "write_kib": 1573194.1},
-                       "fwd": {"fetch_kib": 991201.6, "write_kib": 786618.8},
-                       "adj": {"fetch_kib": 1036113.8, "write_kib": 1573108.6}},
+        "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1841636.4, "write_kib": 1573195.8},
+                       "fwd": {"fetch_kib": 990142.6, "write_kib": 786618.3},
+                       "adj": {"fetch_kib": 1035743.8, "write_kib": 1573112.9}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }

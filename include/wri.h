@@ -55,6 +55,15 @@
  *     max_iter, see results); < 0 = error.  Inputs are validated before any
  *     device work; on error nothing is launched and wri_last_error() gives a
  *     message (thread-local).  No C++ exception crosses this ABI.
+ *   - Tiling: the batched solver times candidate slab tiles on the first call
+ *     of each batch shape and caches the fastest; once at most 2^25 cells
+ *     still iterate it switches the tuned recomputed-t tile to 16-plane slabs
+ *     (more workgroups for the last systems; only the summation order of a
+ *     float64 reduction changes).  Environment overrides, for tests and
+ *     experiments: WRI_TILE="w,ry,tz,pf[,order]" forces a tile (and turns the
+ *     switch off), WRI_TAIL_TILE (same form, or "0" for no switch) and
+ *     WRI_TAIL_CELLS set the switch; WRI_VERBOSE=1 prints the tiles and, every
+ *     30 s, the progress of long solves to stderr.
  */
 #ifndef WRI_H
 #define WRI_H
