@@ -365,3 +365,26 @@ def test_host_code_under_address_and_undefined_behaviour_sanitizers():
     tail = (proc.stdout + proc.stderr)[-3000:]
     assert proc.returncode == 0, tail
     assert "passed" in proc.stdout and "ERROR: AddressSanitizer" not in tail and "runtime error" not in tail
+
+
+def test_probe_entry_points_validate_before_device_work():
+    """The streaming probes size and check their arguments on the host: bad
+    mixes, odd or non-positive sizes, tile shapes that are not multiples of
+    64 x 16 x 32, missing workspace and a NULL result pointer are rejected
+    before any launch."""
+    L = wri.lib()
+    assert L.wri_stream_probe_bytes(4, 1 << 10) == 0
+    assert L.wri_stream_probe_bytes(0, 1023) == 0
+    assert L.wri_stream_probe_bytes(1, 1 << 10) > 0
+    assert L.wri_tile_probe_bytes(128, 128, 128, 48) > 48 * 128 ** 3 * 8 * 3
+    for shape in ((100, 128, 128, 1), (128, 24, 128, 1), (128, 128, 40, 1), (128, 128, 128, 0), (0, 16, 32, 1)):
+        assert L.wri_tile_probe_bytes(*shape) == 0, shape
+    out = ctypes.c_double(0.0)
+    assert L.wri_tile_probe(100, 128, 128, 1, 3, None, 0, None, ctypes.byref(out)) == wri.EINVAL
+    assert L.wri_tile_probe(128, 128, 128, 1, 0, None, 0, None, ctypes.byref(out)) == wri.EINVAL
+    assert L.wri_tile_probe(128, 128, 128, 1, 3, None, 0, None, None) == wri.EINVAL
+    assert L.wri_tile_probe(128, 128, 128, 1, 3, None, 0, None, ctypes.byref(out)) == wri.ENOWS
+    assert L.wri_tile_probe(4096, 4096, 256, 64, 3, None, 0, None, ctypes.byref(out)) == wri.EINVAL
+    assert L.wri_stream_probe(5, 1 << 10, 3, None, 0, None, ctypes.byref(out)) == wri.EINVAL
+    assert L.wri_stream_probe(1, 1 << 10, 3, None, 0, None, ctypes.byref(out)) == wri.ENOWS
+    assert out.value == 0.0
