@@ -331,7 +331,7 @@ def tail_probe(dev, tiles, k1=600, k2=800):
 
 def precond_bench(dev, steps, rtols=(1e-4, 1e-5), ref_rtol=1e-7, sample=(0, 16, 32, 47)):
     """The 128^3 workload (48 systems) solved by the plain batched CGLS (the
-    headline method) and by the V-cycle-preconditioned CGLS (row f4): seconds
+    headline method) and by the V-cycle-preconditioned CGLS (fewer iterations): seconds
     per objective-and-gradient evaluation, iteration counts, and the wavefield
     and source-weight errors of both against a tight preconditioned solve
     (rtol 1e-7, about what float32 storage resolves) of the same systems, on

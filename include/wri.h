@@ -56,14 +56,19 @@
  *     device work; on error nothing is launched and wri_last_error() gives a
  *     message (thread-local).  No C++ exception crosses this ABI.
  *   - Tiling: the batched solver times candidate slab tiles on the first call
- *     of each batch shape and caches the fastest; once at most 2^25 cells
- *     still iterate it switches the tuned recomputed-t tile to 16-plane slabs
- *     (more workgroups for the last systems; only the summation order of a
- *     float64 reduction changes).  Environment overrides, for tests and
- *     experiments: WRI_TILE="w,ry,tz,pf[,order]" forces a tile (and turns the
- *     switch off), WRI_TAIL_TILE (same form, or "0" for no switch) and
- *     WRI_TAIL_CELLS set the switch; WRI_VERBOSE=1 prints the tiles and, every
- *     30 s, the progress of long solves to stderr.
+ *     of each batch shape and caches the fastest.  As systems stop, a tuned
+ *     recomputed-t tile changes its z-slab (the tuned one, halved down to 16
+ *     planes) to the one with the least modelled time for the systems still
+ *     iterating: rounds of workgroups on the chip times planes per slab
+ *     (only the summation order of a float64 reduction changes).  Environment
+ *     overrides, for tests and experiments: WRI_TILE="w,ry,tz,pf[,order]"
+ *     forces a tile (any supported shape whose tile count fits the
+ *     partial-sum slots; the slab then stays), WRI_TAIL_UNITS sets the chip's
+ *     resident workgroups of the model (and applies it to a forced tile),
+ *     WRI_TAIL_TILE (same form as WRI_TILE, or "0" for no change) asks instead
+ *     for one switch to that tile once at most WRI_TAIL_CELLS cells (default
+ *     2^25) still iterate; WRI_VERBOSE=1 prints the tiles, the slab changes
+ *     and, every 30 s, the progress of long solves to stderr.
  */
 #ifndef WRI_H
 #define WRI_H
@@ -449,8 +454,9 @@ int wri_objective_grad_offgrid(const wri_grid* grids, int32_t n_grids, const flo
 
 /* Kernel time of the last WRI_FLAG_TIMING call on this thread (HIP event
  * pairs around every fused launch; one launch covers every active system).
- * Bytes are algorithmic: per cell, forward 36 B (+24 B for the x update on
- * even iterations k >= 2), adjoint 36 B; halo re-reads are not counted. */
+ * Bytes are algorithmic: per cell, forward 36 B with t stored, 28 B when the
+ * adjoint pass recomputes t (+24 B for the x update on even iterations
+ * k >= 2), adjoint 36 B; halo re-reads are not counted. */
 typedef struct {
   double  fwd_ms, adj_ms;                /* summed durations of the fused launches       */
   int64_t fwd_launches, adj_launches;
@@ -466,14 +472,15 @@ typedef struct {
                                                            in the adjoint pass, 3 as 2 with
                                                            two planes of prefetch; block
                                                            order)                        */
-  int32_t reserved_;
+  int32_t tail_switches;                 /* changes of the tiling during the solve (the
+                                            convergence tail, see Tiling above)          */
 } wri_timing;
 
 /* Fills *out; WRI_EINVAL if no timed call has completed on this thread. */
 int wri_kernel_times(wri_timing* out);
 
-/* Objective and gradient with the preconditioned CGLS (row f4 of the build:
- * fewer iterations).  Beyond the paper, whose only reducer of the iteration
+/* Objective and gradient with the preconditioned CGLS (fewer CGLS
+ * iterations).  Beyond the paper, whose only reducer of the iteration
  * count is the adaptive tolerance of Algorithm 2: S is preconditioned on the
  * right by one multigrid V(1,1) cycle of the complex-shifted Helmholtz
  * operator A_beta = L_h + diag(omega^2 (1 - i beta) m - i omega b), beta = 1/2

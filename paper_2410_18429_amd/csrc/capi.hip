@@ -74,7 +74,7 @@ const TileCfg kCands[] = {
     {8, 1, 32, 1, 2}, {8, 1, 32, 1, 4}, {8, 1, 32, 1, 8}, {4, 2, 32, 1, 2},
     {8, 1, 32, 2, 4}, {8, 2, 32, 2, 4}, {4, 4, 32, 2, 4}, {4, 2, 32, 2, 4}, {8, 1, 32, 2, 0},
     {8, 1, 32, 3, 4}, {4, 2, 32, 3, 4}, {4, 2, 64, 2, 4}, {4, 2, 16, 2, 4}, {8, 1, 64, 3, 4},
-    {4, 4, 32, 1, 4},
+    {4, 4, 32, 1, 4}, {8, 4, 64, 2, 4}, {8, 4, 32, 2, 4}, {4, 4, 64, 2, 4}, {8, 4, 32, 1, 4},
 };
 constexpr int kNumCands = sizeof(kCands) / sizeof(kCands[0]);
 
@@ -429,7 +429,12 @@ int set_config(Ctx& C, const TileCfg& cfg) {
   C.hgd.resize(C.groups.size());
   int b0 = 0;
   for (size_t gi = 0; gi < C.groups.size(); ++gi) {
-    const Tiling t = make_tiling(cfg, C.grids[C.groups[gi].grid]);
+    const wri_grid& g = C.grids[C.groups[gi].grid];
+    const Tiling t = make_tiling(cfg, g);
+    // each system has max_tiles(g) partial-sum slots (the layout's count)
+    if (!cfg_supported(cfg) || t.ntiles() > max_tiles(g))
+      return fail(WRI_EINVAL, "tile w=%d ry=%d tz=%d pf=%d: %d tiles per system, %d partial slots", cfg.w, cfg.ry,
+                  cfg.tz, cfg.pf, t.ntiles(), max_tiles(g));
     C.tiling[gi] = t;
     GroupDesc& d = C.hgd[gi];
     d.rhs0 = C.groups[gi].rhs0;
@@ -459,37 +464,114 @@ int set_config(Ctx& C, const TileCfg& cfg) {
 
 const TileCfg& cur_cfg(const Ctx& C) { return C.tiling.front().cfg; }
 
-// Convergence tail: once the systems still iterating hold few cells, the
-// tiling tuned for the full batch leaves compute units idle (one 128^3 system
-// is 64 workgroups of the 64 x 16 x 32 tile on 256 compute units), so the
-// solve switches, at an iteration boundary, to the same tile with 16-plane
-// slabs (twice the workgroups).  Measured steady state: the same time on the
-// full 48-system 128^3 batch, 0.084 against 0.177 ms per iteration for one
-// 128^3 system, 0.293 against 0.293 for eight, 0.530 against 0.538 for
-// sixteen; 0.243 against 0.264 for one 256 x 256 x 192 system.  Only for the
-// recomputed-t march chosen by the autotuner, at <= 2^25 cells still
-// iterating; WRI_TAIL_TILE ("w,ry,tz,pf[,order]", or "0" for no switch) and
-// WRI_TAIL_CELLS override the tile and the threshold (tests, experiments).
+// the tile counts of t fit every group's partial-sum slots
+bool tiles_fit(const Ctx& C, const TileCfg& t) {
+  for (const auto& G : C.groups)
+    if (make_tiling(t, C.grids[G.grid]).ntiles() > max_tiles(C.grids[G.grid])) return false;
+  return true;
+}
+
+// Convergence tail.  Once few systems still iterate, the tiling tuned for the
+// full batch leaves compute units idle, or ends every launch with a partly
+// filled round of workgroups.  At every chunk boundary the solve takes the
+// z-slab of the tuned tile's shape (the tuned slab, halved down to 16 planes)
+// with the least modelled time for the systems still iterating,
+//   rounds x planes,  rounds = ceil(workgroups / resident workgroups of the
+//   chip),  planes = min(slab, nz) + 2
+// (the adjoint pass forms t one plane beyond each face of its slab; the chip
+// holds compute units x the adjoint kernel's resident workgroups per unit).
+// Measured steady state, 128^3 workload, 64 x 32 tile, ms per iteration for
+// slabs of 64 / 32 / 16 planes: 48 systems 1.497 / 1.503 / 1.599, 24 systems
+// 0.880 / 0.777 / 0.812, 16 systems 0.512 / 0.521 / 0.565, 12 systems 0.456 /
+// 0.465 / 0.416, 8 systems 0.418 / 0.277 / 0.288, 4 systems 0.386 / 0.237 /
+// 0.161; the model picks the fastest slab in each row.  Only for a
+// recomputed-t tile chosen by the autotuner; WRI_TAIL_UNITS sets the chip's
+// resident workgroups and applies the model to a forced tile too, and
+// WRI_TAIL_TILE ("w,ry,tz,pf[,order]", or "0" for no switch) instead asks for
+// one switch to that tile once at most WRI_TAIL_CELLS cells (default 2^25)
+// still iterate (tests, experiments).
 constexpr int kTailTZ = 16;
-constexpr int64_t kTailCells = (int64_t)1 << 25;
-bool tail_config(const TileCfg& main, bool forced_main, TileCfg* out, int64_t* max_cells) {
-  *max_cells = kTailCells;
-  if (const char* e = getenv("WRI_TAIL_CELLS"); e != nullptr && *e) *max_cells = atoll(e);
+constexpr int kTailFacePlanes = 2;
+struct TailPlan {
+  int kind = 0;              // 0: none; 1: one switch to tile (WRI_TAIL_TILE); 2: slab by the model
+  TileCfg tile{0, 0, 0, 0, 0};
+  int64_t max_cells = 0;     // kind 1
+  int64_t units = 0;         // kind 2: resident workgroups of the chip
+  int full_tz = 0;           // kind 2: the model's slab for the whole batch
+};
+
+// The slab of P.tile's shape with the least modelled time for the systems
+// flagged in active (ties keep the longer slab).
+int model_tz(const Ctx& C, const TailPlan& P, const std::vector<char>& active) {
+  int best_tz = P.tile.tz;
+  double best_cost = -1.0;
+  for (int tz = P.tile.tz; tz >= kTailTZ; tz /= 2) {
+    TileCfg t = P.tile;
+    t.tz = tz;
+    if (!cfg_supported(t) || !tiles_fit(C, t)) continue;
+    int64_t blocks = 0;
+    int planes = 0;
+    for (int p = 0; p < C.n_sys; ++p) {
+      if (!active[p]) continue;
+      const wri_grid& g = C.grids[C.sys[C.L.order[p]].grid];
+      blocks += make_tiling(t, g).ntiles();
+      planes = std::max(planes, std::min(tz, g.nz) + kTailFacePlanes);
+    }
+    const double cost = (double)((blocks + P.units - 1) / P.units) * planes;
+    if (best_cost < 0.0 || cost < best_cost) {
+      best_cost = cost;
+      best_tz = tz;
+    }
+  }
+  return best_tz;
+}
+
+TailPlan tail_plan(const Ctx& C, const TileCfg& main, bool forced_main) {
+  TailPlan P;
   const char* e = getenv("WRI_TAIL_TILE");
   if (e != nullptr && *e) {
-    if (*e == '0') return false;
+    if (*e == '0') return P;
     TileCfg t{0, 0, 0, 0, 0};
     const int got = sscanf(e, "%d,%d,%d,%d,%d", &t.w, &t.ry, &t.tz, &t.pf, &t.order);
-    if (got < 4 || !cfg_supported(t)) return false;
+    if (got < 4 || !cfg_supported(t)) return P;
     if (got == 4) t.order = 0;
+    if (!tiles_fit(C, t)) return P;
     // t is produced and consumed within one iteration, so any march may follow
-    *out = t;
-    return true;
+    P.kind = 1;
+    P.tile = t;
+    P.max_cells = (int64_t)1 << 25;
+    if (const char* c = getenv("WRI_TAIL_CELLS"); c != nullptr && *c) P.max_cells = atoll(c);
+    return P;
   }
-  if (forced_main || main.pf < 2 || main.tz <= kTailTZ) return false;
-  *out = main;
-  out->tz = kTailTZ;
-  return cfg_supported(*out);
+  const char* u = getenv("WRI_TAIL_UNITS");
+  const bool u_set = u != nullptr && *u;
+  if ((forced_main && !u_set) || main.pf < 2 || main.tz <= kTailTZ) return P;
+  int64_t units = 0;
+  if (u_set) {
+    units = atoll(u);
+  } else {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, C.dev) != hipSuccess) return P;
+    units = (int64_t)cus * adj_blocks_per_cu(main);
+  }
+  if (units <= 0) return P;
+  P.kind = 2;
+  P.tile = main;
+  P.units = units;
+  P.full_tz = model_tz(C, P, std::vector<char>(C.n_sys, 1));
+  return P;
+}
+
+// Plan kind 2: the tile for the systems still iterating.  The tuned slab stays
+// while the model picks for them what it picks for the whole batch (the
+// autotuner measured the whole batch; the model only tracks the change).
+TileCfg tail_tile(const Ctx& C, const std::vector<SysState>& hs, const TailPlan& P) {
+  std::vector<char> active(C.n_sys);
+  for (int p = 0; p < C.n_sys; ++p) active[p] = hs[p].status == kActive;
+  TileCfg t = P.tile;
+  const int tz = model_tz(C, P, active);
+  if (tz != P.full_tz) t.tz = tz;
+  return t;
 }
 
 // Switch the tiling between two iterations: the new group table, then the
@@ -557,21 +639,18 @@ bool verbose() {
   return v;
 }
 
-// WRI_TILE="w,ry,tz,pf[,order]" forces one of the candidate tiles (tests, experiments)
-bool forced_tile(TileCfg* out) {
+// WRI_TILE="w,ry,tz,pf[,order]" forces a tile (tests, experiments): any
+// supported shape whose tile count fits the partial-sum slots of every grid
+bool forced_tile(const Ctx& C, TileCfg* out) {
   const char* e = getenv("WRI_TILE");
   if (e == nullptr || *e == 0) return false;
   TileCfg t{0, 0, 0, 0, 0};
   const int got = sscanf(e, "%d,%d,%d,%d,%d", &t.w, &t.ry, &t.tz, &t.pf, &t.order);
-  if (got < 4) return false;
+  if (got < 4 || !cfg_supported(t)) return false;
   if (got == 4) t.order = 0;
-  for (int i = 0; i < kNumCands; ++i)
-    if (kCands[i].w == t.w && kCands[i].ry == t.ry && kCands[i].tz == t.tz && kCands[i].pf == t.pf &&
-        kCands[i].order == t.order) {
-      *out = t;
-      return true;
-    }
-  return false;
+  if (!tiles_fit(C, t)) return false;
+  *out = t;
+  return true;
 }
 
 // Time a few real iterations of the whole batch per candidate tile shape and
@@ -710,12 +789,13 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
   }
 
   TileCfg main_cfg = kCands[0];  // the tile of the full batch (reported by the timing)
+  int n_switches = 0;            // tiling changes of the convergence tail
   if (C.n_sys > 0) {
     WRI_HIP(hipMemcpyAsync(C.dsys, C.hsys.data(), sizeof(SysDev) * C.n_sys, hipMemcpyHostToDevice, C.st));
     int rc = upload_receivers(C);
     if (rc != WRI_OK) return rc;
     TileCfg forced;
-    const bool is_forced = forced_tile(&forced);
+    const bool is_forced = forced_tile(C, &forced);
     if (is_forced) rc = set_config(C, forced);
     else if (!(C.flags & WRI_FLAG_NO_AUTOTUNE)) rc = autotune(C);
     else rc = set_config(C, kCands[0]);
@@ -737,9 +817,7 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
     int64_t launched = 0;
     auto last_report = std::chrono::steady_clock::now();
     main_cfg = cur_cfg(C);
-    TileCfg tail_cfg = main_cfg;
-    int64_t tail_cells = 0;
-    bool tail_pending = tail_config(main_cfg, is_forced, &tail_cfg, &tail_cells);
+    TailPlan tail = tail_plan(C, main_cfg, is_forced);
     EventPool pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fwd, ev_adj;
     if (timing) g_times = KernelTimes();
@@ -816,18 +894,29 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
         }
       }
       if (!active) break;
-      if (tail_pending) {
+      if (tail.kind == 1) {
         int64_t act_cells = 0;
         for (int p = 0; p < C.n_sys; ++p)
           if (hs[p].status == kActive) act_cells += cells(C.grids[C.sys[L.order[p]].grid]);
-        if (act_cells <= tail_cells) {
-          rc = switch_tiling(C, tail_cfg);
+        if (act_cells <= tail.max_cells) {
+          rc = switch_tiling(C, tail.tile);
           if (rc != WRI_OK) return rc;
-          tail_pending = false;
+          tail.kind = 0;
+          ++n_switches;
           if (verbose())
             fprintf(stderr, "[wri] iteration %lld: %d systems (%lld cells) iterating, tile w=%d ry=%d tz=%d pf=%d order=%d\n",
-                    (long long)launched, n_active, (long long)act_cells, tail_cfg.w, tail_cfg.ry, tail_cfg.tz,
-                    tail_cfg.pf, tail_cfg.order);
+                    (long long)launched, n_active, (long long)act_cells, tail.tile.w, tail.tile.ry, tail.tile.tz,
+                    tail.tile.pf, tail.tile.order);
+        }
+      } else if (tail.kind == 2) {
+        const TileCfg t = tail_tile(C, hs, tail);
+        if (t.tz != cur_cfg(C).tz) {
+          rc = switch_tiling(C, t);
+          if (rc != WRI_OK) return rc;
+          ++n_switches;
+          if (verbose())
+            fprintf(stderr, "[wri] iteration %lld: %d systems iterating, slab %d planes\n", (long long)launched,
+                    n_active, t.tz);
         }
       }
       if (launched > (int64_t)C.max_iter + 2)
@@ -841,6 +930,7 @@ int run_batched(Ctx& C, float* const* grad, std::vector<SysState>& hs) {
       g_times.t.tile_w = c.w; g_times.t.tile_ry = c.ry; g_times.t.tile_tz = c.tz;
       g_times.t.tile_pf = c.pf; g_times.t.tile_order = c.order;
     }
+    g_times.t.tail_switches = n_switches;
     g_times.valid = true;
   }
   // objective partials and gradient, per grid

@@ -1745,7 +1745,7 @@ k_adj_rc(const SysDev* __restrict__ sysv, SysState* __restrict__ stv, const doub
 // dispatch over the supported tile shapes
 // ---------------------------------------------------------------------------
 
-#define WRI_TILE_LIST(X) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(2, 8)
+#define WRI_TILE_LIST(X) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(2, 8) X(8, 4)
 
 bool cfg_supported(const TileCfg& c) {
 #define X(W_, R_) if (c.w == W_ && c.ry == R_) return c.tz >= 1 && c.tz <= 64 && c.pf >= 0 && c.pf <= 3;
@@ -1780,6 +1780,21 @@ hipError_t launch_fwd(const TileCfg& c, const SysDev* sys, SysState* st, const d
   WRI_TILE_LIST(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+int adj_blocks_per_cu(const TileCfg& c) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define X(W_, R_)                                                                                   \
+  if (c.w == W_ && c.ry == R_) {                                                                    \
+    if (c.pf == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_pf<W_, R_>, 64 * W_, 0);  \
+    else if (c.pf == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_rc<W_, R_, 1>, 64 * W_, 0); \
+    else if (c.pf == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_rc<W_, R_, 2>, 64 * W_, 0); \
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj<W_, R_>, 64 * W_, 0);         \
+  }
+  WRI_TILE_LIST(X)
+#undef X
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_adj(const TileCfg& c, const SysDev* sys, SysState* st, const double* part_d, double* part_s,

@@ -129,6 +129,8 @@ hipError_t launch_finalize(const SysDev* sys, SysState* st, const double* part_j
 hipError_t launch_zero_f32(float* p, size_t n, hipStream_t s);
 int grad_blocks(int n);
 bool cfg_supported(const TileCfg& c);
+// workgroups of the adjoint kernel of tile c resident on one compute unit (0 on error)
+int adj_blocks_per_cu(const TileCfg& c);
 
 // single-operator and unfused kernels (test hook and the plain baseline)
 hipError_t launch_apply(int nx, int ny, int nz, int nb, double h2inv, double sp_scale, double inv_nb,

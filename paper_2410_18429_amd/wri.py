@@ -73,7 +73,7 @@ class WriTiming(ctypes.Structure):
                 ("adj_launches_full", ctypes.c_int64), ("fwd_bytes_full", c_double),
                 ("adj_bytes_full", c_double), ("tile_w", ctypes.c_int32), ("tile_ry", ctypes.c_int32),
                 ("tile_tz", ctypes.c_int32), ("tile_pf", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32)]
+                ("tail_switches", ctypes.c_int32)]
 
 
 class WriAwriOptions(ctypes.Structure):

@@ -160,7 +160,7 @@ def test_solve_parity_production_tiles_multi_slab(monkeypatch, mode):
         _MULTI_SLAB_REF[mode] = oracle.objective_grad(p, mode=mode, normal_solver="woodbury")
     ref = _MULTI_SLAB_REF[mode]
     gref = ref["g"][0].reshape(-1)
-    for tile in ("4,4,32,2,4", "4,2,16,2,4"):
+    for tile in ("8,4,64,2,4", "4,4,32,2,4", "4,2,16,2,4"):
         monkeypatch.setenv("WRI_TILE", tile)
         _say(f"multi-slab 70x20x67 mode={mode} tile={tile}")
         b = wri.Batch(p, device=DEV, mode=mode)
@@ -211,6 +211,51 @@ def test_tail_tiling_switch_parity(monkeypatch, mode, tail):
     _say(f"tail switch 4,4,32,2,4 -> {tail}, mode={mode}")
     u1 = wri.alloc_wavefields(b)
     J, grads, res = wri.objective_grad(b, max_iter=60000, u_out=u1)
+    g = grads[0].cpu().numpy().astype(np.float64)
+    for i in range(len(p.systems)):
+        eu = rel(_np(u1[i]), ref["u"][i])
+        du = rel(_np(u1[i]), _np(u0[i]))
+        eJ = abs(res[i]["J"] - ref["J_sys"][i]) / ref["J_sys"][i]
+        _say(f"  sys {i}: iters {res[i]['iters']} (no switch {r0[i]['iters']}) u err {eu:.2e} "
+             f"vs no switch {du:.2e} J err {eJ:.2e}")
+        assert res[i]["status"] == "converged", res[i]
+        assert abs(res[i]["iters"] - r0[i]["iters"]) <= max(2, 0.02 * r0[i]["iters"]), i
+        assert eu < 1e-4 and eJ < 1e-4 and du < 5e-5, i
+        if mode == "estimate":
+            assert abs(res[i]["alpha_ls"] - ref["alpha"][i]) < 1e-4 * abs(ref["alpha"][i]), i
+    assert abs(J - ref["J"]) < 1e-4 * ref["J"]
+    assert rel(g, gref) < 1e-3
+
+
+@pytest.mark.parametrize("mode", ["estimate", "known"])
+def test_tail_slab_model_switches(monkeypatch, mode):
+    """The model-driven convergence tail on the 64 x 32 tile with 64-plane
+    slabs.  On 70 x 20 x 64 (one slab of 64 planes, two of 32, four of 16) with
+    the chip's resident workgroups set to 8, the model keeps 64 planes for the
+    four systems and changes the slab as they stop (16 planes for three, 32 for
+    two, 16 for one), each change folding the partials of ||s||^2 to the new
+    tile count.  Against the exact minimiser (u, alpha, J within 1e-4, g within
+    1e-3) and the same solve without switches (iterations within 2 %, u within
+    5e-5: only the summation order of ||t||^2 changes)."""
+    p = wri_synth.custom_problem((70, 20, 64), nb=6, n_src=2, n_rec=10, seed=7, freqs=(6.0, 9.0),
+                                 rtol=PARITY_RTOL)
+    _say(f"tail slab model 70x20x64, mode={mode}")
+    ref = oracle.objective_grad(p, mode=mode, normal_solver="woodbury")
+    gref = ref["g"][0].reshape(-1)
+    monkeypatch.setenv("WRI_TILE", "8,4,64,2,4")
+    monkeypatch.setenv("WRI_TAIL_TILE", "0")
+    b = wri.Batch(p, device=DEV, mode=mode)
+    u0 = wri.alloc_wavefields(b)
+    _, _, r0 = wri.objective_grad(b, max_iter=60000, u_out=u0, flags=wri.FLAG_TIMING)
+    assert wri.kernel_times()["tail_switches"] == 0
+    monkeypatch.delenv("WRI_TAIL_TILE")
+    monkeypatch.setenv("WRI_TAIL_UNITS", "8")
+    u1 = wri.alloc_wavefields(b)
+    J, grads, res = wri.objective_grad(b, max_iter=60000, u_out=u1, flags=wri.FLAG_TIMING)
+    n_sw = wri.kernel_times()["tail_switches"]
+    stops = sorted(r["iters"] for r in r0)
+    _say(f"  stops {stops}, tiling switches {n_sw}")
+    assert n_sw >= 1
     g = grads[0].cpu().numpy().astype(np.float64)
     for i in range(len(p.systems)):
         eu = rel(_np(u1[i]), ref["u"][i])
@@ -566,12 +611,12 @@ def test_full_size_differentiation_workload():
 TILES = ["4,4,32,0,0", "4,4,32,1,1", "4,2,32,0,1", "4,2,32,1,1", "4,2,32,1,0", "4,2,16,0,0", "8,1,32,1,1",
          "8,2,32,1,0", "2,8,32,0,0", "4,1,64,1,1", "8,1,32,1,2", "8,1,32,1,4", "4,2,32,1,2", "8,1,32,2,4",
          "4,2,32,2,4", "4,4,32,2,4", "8,2,32,2,4", "8,1,32,2,0", "8,1,32,3,4", "4,2,32,3,4", "4,2,16,2,4",
-         "8,1,64,3,4"]
+         "8,1,64,3,4", "8,4,64,2,4", "8,4,32,2,4", "4,4,64,2,4", "8,4,32,1,4"]
 
 # tiles whose adjoint pass recomputes t = S p_k, and a stored-t tile of the same shape
 RECOMPUTE_PAIRS = (("8,1,32,1,4", "8,1,32,2,4"), ("4,2,32,1,1", "4,2,32,2,4"), ("4,4,32,1,1", "4,4,32,2,4"),
                    ("8,2,32,1,1", "8,2,32,2,4"), ("8,1,32,1,0", "8,1,32,2,0"), ("8,1,32,1,1", "8,1,32,3,4"),
-                   ("4,2,32,1,2", "4,2,32,3,4"))
+                   ("4,2,32,1,2", "4,2,32,3,4"), ("8,4,32,1,4", "8,4,32,2,4"))
 
 
 def test_large_workload_frequency_batch():
