@@ -60,11 +60,11 @@ def kernel_label(dominant, pf):
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "9cbfa26d504e932d",
+    "sources_sha256": "386b22ece6da777a",
     "tiles": {
-        "4,4,32,2,4": {"fwd_x": {"fetch_kib": 1841636.4, "write_kib": 1573195.8},
-                       "fwd": {"fetch_kib": 990142.6, "write_kib": 786618.3},
-                       "adj": {"fetch_kib": 1035743.8, "write_kib": 1573112.9}},
+        "8,4,64,2,4": {"fwd_x": {"fetch_kib": 1795154.1, "write_kib": 1573210.2},
+                       "fwd": {"fetch_kib": 952340.5, "write_kib": 786605.8},
+                       "adj": {"fetch_kib": 936057.9, "write_kib": 1573038.0}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
@@ -303,7 +303,7 @@ def tail_probe(dev, tiles, k1=600, k2=800):
     import wri_synth
     from paper_2410_18429_amd import wri
     out = []
-    for name, counts in (("differentiation", (1, 2, 3, 4, 6, 8, 12, 16, 48)), ("large", (1, 2, 3, 4, 6, 8))):
+    for name, counts in (("differentiation", (1, 2, 4, 6, 8, 12, 16, 24, 32, 48)), ("large", (1, 2, 4, 8))):
         prob = wri_synth.make_config(name, seed=0)
         nsys = len(prob.systems)
         for tile in tiles:
