@@ -75,6 +75,7 @@ const TileCfg kCands[] = {
     {8, 1, 32, 2, 4}, {8, 2, 32, 2, 4}, {4, 4, 32, 2, 4}, {4, 2, 32, 2, 4}, {8, 1, 32, 2, 0},
     {8, 1, 32, 3, 4}, {4, 2, 32, 3, 4}, {4, 2, 64, 2, 4}, {4, 2, 16, 2, 4}, {8, 1, 64, 3, 4},
     {4, 4, 32, 1, 4}, {8, 4, 64, 2, 4}, {8, 4, 32, 2, 4}, {4, 4, 64, 2, 4}, {8, 4, 32, 1, 4},
+    {8, 4, 64, 2, 8}, {8, 4, 64, 2, 2},
 };
 constexpr int kNumCands = sizeof(kCands) / sizeof(kCands[0]);
 

@@ -479,7 +479,7 @@ def test_degenerate_grids(shape):
     assert rel(_np(u[0]), ref["u"][0]) < 1e-4
 
 
-@pytest.mark.parametrize("tile", ["4,4,32,2,4", "8,1,32,3,4", "4,2,16,2,4"])
+@pytest.mark.parametrize("tile", ["8,4,64,2,4", "4,4,32,2,4", "8,1,32,3,4", "4,2,16,2,4"])
 def test_degenerate_grids_recomputed_t(monkeypatch, tile):
     """The recomputed-t march on grids of one plane, one row, one column and a
     ragged slab (z-slab 16 over 33 planes: slabs of 16, 16 and 1), against the
@@ -693,22 +693,25 @@ def test_tile_invariance(monkeypatch):
 
 def test_block_orders_give_identical_bits(monkeypatch):
     """System-major, tile-major and bundled block orders (bundles of 2, 4 and
-    8 over 5 systems: full and ragged bundles) only change which block does
-    which (system, tile): every tile's arithmetic and the fixed-order sums of
-    the per-tile partials are the same, so the results are bit-identical."""
+    8 over 5 systems: full and ragged bundles; a stored-t and a recomputed-t
+    tile) only change which block does which (system, tile): every tile's
+    arithmetic and the fixed-order sums of the per-tile partials are the same,
+    so the results are bit-identical."""
     _say("block orders")
     p = wri_synth.custom_problem((70, 20, 12), nb=2, n_src=5, n_rec=8, seed=23, freqs=(9.0,), rtol=0.0)
-    outs = {}
-    for t in ("8,1,32,1,0", "8,1,32,1,1", "8,1,32,1,2", "8,1,32,1,4", "8,1,32,1,8"):
-        monkeypatch.setenv("WRI_TILE", t)
-        u, res = wri.solve(wri.Batch(p, device=DEV), max_iter=14)
-        outs[t] = (u, res)
-    monkeypatch.delenv("WRI_TILE")
-    ref = outs["8,1,32,1,0"]
-    for t, (u, res) in outs.items():
-        for i in range(len(p.systems)):
-            assert torch.equal(u[i], ref[0][i]), (t, i)
-            assert res[i]["alpha"] == ref[1][i]["alpha"], (t, i)
+    for group in (("8,1,32,1,0", "8,1,32,1,1", "8,1,32,1,2", "8,1,32,1,4", "8,1,32,1,8"),
+                  ("8,4,64,2,0", "8,4,64,2,2", "8,4,64,2,4", "8,4,64,2,8")):
+        outs = {}
+        for t in group:
+            monkeypatch.setenv("WRI_TILE", t)
+            u, res = wri.solve(wri.Batch(p, device=DEV), max_iter=14)
+            outs[t] = (u, res)
+        monkeypatch.delenv("WRI_TILE")
+        ref = outs[group[0]]
+        for t, (u, res) in outs.items():
+            for i in range(len(p.systems)):
+                assert torch.equal(u[i], ref[0][i]), (t, i)
+                assert res[i]["alpha"] == ref[1][i]["alpha"], (t, i)
 
 
 @pytest.mark.parametrize("mode", ["estimate", "known"])
