@@ -60,11 +60,11 @@ def kernel_label(dominant, pf):
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "386b22ece6da777a",
+    "sources_sha256": "bd9141f0445060a5",
     "tiles": {
-        "8,4,64,2,4": {"fwd_x": {"fetch_kib": 1795154.1, "write_kib": 1573210.2},
-                       "fwd": {"fetch_kib": 952340.5, "write_kib": 786605.8},
-                       "adj": {"fetch_kib": 936057.9, "write_kib": 1573038.0}},
+        "8,4,64,2,2": {"fwd_x": {"fetch_kib": 1777991.1, "write_kib": 1573167.6},
+                       "fwd": {"fetch_kib": 968321.1, "write_kib": 786604.6},
+                       "adj": {"fetch_kib": 931326.3, "write_kib": 1573036.7}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
