@@ -390,8 +390,8 @@ def precond_bench(dev, steps, rtols=(1e-4, 1e-5), ref_rtol=1e-7, sample=(0, 16, 
 def stream_ceilings(wri, dev, n=1 << 27, reps=5):
     """GB/s of the library's streaming probe for each access mix (copy, forward,
     forward with the x update, adjoint) over n complex64 elements per array, and
-    of the forward mix in the fused kernels' tile order over the 48 grids of
-    128^3 of the workload ("fwd_tiles")."""
+    of the forward mix in a tiled plane-by-plane order (64 x 16 x 32 tiles) over
+    the 48 grids of 128^3 of the workload ("fwd_tiles")."""
     out = {mix: wri.stream_probe(mix, n, reps, device=dev) for mix in ("copy", "fwd", "fwd_x", "adj")}
     out["fwd_tiles"] = wri.tile_probe(128, 128, 128, 48, reps, device=dev)
     return out
@@ -959,7 +959,7 @@ def main():
     # practical streaming ceilings on this device: a plain kernel with the access
     # mix of each fused launch and none of its arithmetic (wri_stream_probe, 2^27
     # complex64 elements per array, best of five launches per variant), and the
-    # forward mix in the fused kernels' own tile order (wri_tile_probe)
+    # forward mix in a tiled plane-by-plane order like the fused kernels' (wri_tile_probe)
     ceil = stream_ceilings(wri, dev)
     pf = kt["tile_pf"]
     if dominant == "fwd":

@@ -530,7 +530,7 @@ size_t wri_stream_probe_bytes(int32_t mix, int64_t n);
 int wri_stream_probe(int32_t mix, int64_t n, int32_t reps, void* ws, size_t ws_bytes, void* stream,
                      double* gbs_out);
 
-/* The same probe in the fused kernels' access pattern: mix 1 (read a, b, m;
+/* The same probe in a tiled access pattern like the fused kernels': mix 1 (read a, b, m;
  * write c; 28 B per cell) over n_sys grids of nx x ny x nz cells, one
  * workgroup of 256 threads per (grid, 64 x 16 x 32 tile), blocks of the same
  * tile of consecutive grids adjacent, marching z through its slab plane by

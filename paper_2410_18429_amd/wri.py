@@ -241,7 +241,8 @@ def stream_probe(mix: str, n: int, reps: int = 5, device="cuda") -> float:
 
 def tile_probe(nx: int, ny: int, nz: int, n_sys: int, reps: int = 5, device="cuda") -> float:
     """wri_tile_probe: GB/s of a plain streaming kernel with the forward pass's
-    byte mix in the fused kernels' tile order over n_sys grids of nx x ny x nz."""
+    byte mix in a tiled plane-by-plane order like the fused kernels' (64 x 16 x 32
+    tiles) over n_sys grids of nx x ny x nz."""
     nbytes = lib().wri_tile_probe_bytes(int(nx), int(ny), int(nz), int(n_sys))
     if nbytes == 0:
         raise WriError(EINVAL, "bad tile probe shape")
