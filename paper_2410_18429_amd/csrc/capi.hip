@@ -449,13 +449,17 @@ int set_config(Ctx& C, const TileCfg& cfg) {
     b0 += d.nrhs * d.ntiles;
   }
   C.nblocks = b0;
-  // XCD chunk: half of the largest system's tiles.  Measured on the 48-system
-  // 128^3 batch (whole solves): halves 18.20 solves/s, whole systems 18.15,
+  // XCD chunk: half of the largest system's tiles, and at least 16 workgroups.
+  // Measured on the 48-system 128^3 batch (whole solves): with the 64 x 16 x 32
+  // tile (64 tiles per system) halves 18.20 solves/s, whole systems 18.15,
   // eighths 18.06, sixteenths 17.58 -- smaller chunks balance the convergence
-  // tail better but lose more halo rows to other XCDs' L2.
+  // tail better but lose more halo rows to other XCDs' L2; with the 64 x 32 x 64
+  // tile (16 tiles per system) chunks of 8, 16 and 32 workgroups took 2.424,
+  // 2.399 and 2.401 s per evaluation.
+  constexpr int kMinXChunk = 16;
   int tmax = 1;
   for (const auto& d : C.hgd) tmax = std::max(tmax, d.ntiles);
-  for (auto& d : C.hgd) d.xchunk = std::max(1, tmax / 2);
+  for (auto& d : C.hgd) d.xchunk = std::max(kMinXChunk, tmax / 2);
   if (!C.hgd.empty()) {
     WRI_HIP(hipMemcpyAsync(C.dgd, C.hgd.data(), sizeof(GroupDesc) * C.hgd.size(), hipMemcpyHostToDevice, C.st));
     WRI_HIP(hipStreamSynchronize(C.st));  // C.hgd may change before an asynchronous copy would finish
@@ -482,10 +486,10 @@ bool tiles_fit(const Ctx& C, const TileCfg& t) {
 // (the adjoint pass forms t one plane beyond each face of its slab; the chip
 // holds compute units x the adjoint kernel's resident workgroups per unit).
 // Measured steady state, 128^3 workload, 64 x 32 tile, ms per iteration for
-// slabs of 64 / 32 / 16 planes: 48 systems 1.497 / 1.503 / 1.599, 24 systems
-// 0.880 / 0.777 / 0.812, 16 systems 0.512 / 0.521 / 0.565, 12 systems 0.456 /
-// 0.465 / 0.416, 8 systems 0.418 / 0.277 / 0.288, 4 systems 0.386 / 0.237 /
-// 0.161; the model picks the fastest slab in each row.  Only for a
+// slabs of 64 / 32 / 16 planes: 48 systems 1.496 / 1.500 / 1.602, 24 systems
+// 0.881 / 0.774 / 0.811, 16 systems 0.511 / 0.521 / 0.564, 12 systems 0.459 /
+// 0.467 / 0.417, 8 systems 0.424 / 0.279 / 0.290, 4 systems 0.385 / 0.235 /
+// 0.163; the model picks the fastest slab in each row.  Only for a
 // recomputed-t tile chosen by the autotuner; WRI_TAIL_UNITS sets the chip's
 // resident workgroups and applies the model to a forced tile too, and
 // WRI_TAIL_TILE ("w,ry,tz,pf[,order]", or "0" for no switch) instead asks for
