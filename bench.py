@@ -60,11 +60,14 @@ def kernel_label(dominant, pf):
 # kernels.hip + capi.hip + wri_impl.hpp + stencil.hpp) and for the tile shape in the key;
 # summary and commands: profiles/fused_cgls_kernels_128cube_48sys_hbm_traffic.md
 TRAFFIC = {
-    "sources_sha256": "bd9141f0445060a5",
+    "sources_sha256": "1d0cda1bde45a0f6",
     "tiles": {
-        "8,4,64,2,2": {"fwd_x": {"fetch_kib": 1777991.1, "write_kib": 1573167.6},
-                       "fwd": {"fetch_kib": 968321.1, "write_kib": 786604.6},
-                       "adj": {"fetch_kib": 931326.3, "write_kib": 1573036.7}},
+        "8,4,64,2,4": {"fwd_x": {"fetch_kib": 1802998.8, "write_kib": 1573197.4},
+                       "fwd": {"fetch_kib": 974238.8, "write_kib": 786607.1},
+                       "adj": {"fetch_kib": 928214.9, "write_kib": 1573033.0}},
+        "8,4,64,2,2": {"fwd_x": {"fetch_kib": 1815348.9, "write_kib": 1573197.9},
+                       "fwd": {"fetch_kib": 1032783.0, "write_kib": 786610.6},
+                       "adj": {"fetch_kib": 976969.6, "write_kib": 1573040.8}},
     },
     "fetch_scale": 2.000, "write_scale": 1.000,
 }
